@@ -1,0 +1,184 @@
+/*
+ * girih.h — C ABI of the MI355X (gfx950) multi-threaded wavefront diamond
+ * (MWD) stencil library.
+ *
+ * The operation (paper: Section "Background / Cache blocking" and Listings
+ * 1-4): T Jacobi steps u^{t+1} = F(u^t) of one of four 3-D stencils on a
+ * structured grid with a fixed Dirichlet halo of width R (the stencil radius),
+ * using two solution buffers whose roles swap after each step.  The blocked
+ * algorithm (Section "Approach", the MWD listing) reorders the point updates
+ * with diamond tiles in (t, y) and a wavefront along z, several threads per
+ * tile; it reaches exactly the result of the naive sweep.
+ *
+ * Conventions
+ *  - All pointers to grid data are DEVICE pointers (HIP) owned by the caller;
+ *    the library never frees them.  Host pointers are only the small
+ *    descriptor structs, coefficient scalars and output arguments.
+ *  - Layout: element (k, j, i) — z, y, x, x fastest — with k in [-h, nz+h),
+ *    j in [-h, ny+h), i in [-h, nx+h) lives at element offset
+ *    ((k+h)*pitch_y + (j+h))*pitch_x + (i+h); pitch_x >= nx+2h,
+ *    pitch_y >= ny+2h.  h must equal the stencil radius (1 or 4).
+ *  - Element type: double (GIRIH_F64) or float (GIRIH_F32); all arithmetic of
+ *    the sweep is done in that type, in the listing's left-to-right order,
+ *    without fused multiply-add.
+ *  - Every function returns 0 (GIRIH_OK) or a negative error code; nothing
+ *    is launched when an argument is rejected.  girih_strerror() names codes.
+ *  - A plan may be used by one host thread / one stream at a time.
+ */
+#ifndef GIRIH_H
+#define GIRIH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GIRIH_OK 0
+#define GIRIH_E_INVALID (-1)     /* bad argument (null pointer, size, halo, pitch, T < 0, ...) */
+#define GIRIH_E_UNSUPPORTED (-2) /* valid request this build has no kernel for */
+#define GIRIH_E_LDS (-3)         /* tile parameters exceed the on-chip budget */
+#define GIRIH_E_HIP (-4)         /* a HIP runtime call failed */
+#define GIRIH_E_NOMEM (-5)       /* device or host allocation failed */
+#define GIRIH_E_NOGPU (-6)       /* no usable gfx950 device */
+
+/* Stencils (paper Listings 1-4; the 25-point constant stencil is the
+ * first-order Jacobi form of Listing 3's bracketed term). */
+typedef enum {
+    GIRIH_7PT_CONST = 0,  /* c0, c1 scalars                         */
+    GIRIH_7PT_VAR = 1,    /* 7 coefficient arrays C0..C6            */
+    GIRIH_25PT_CONST = 2, /* c0..c4 scalars, radius 4               */
+    GIRIH_25PT_VAR = 3    /* 13 coefficient arrays C00..C12, R = 4  */
+} girih_stencil;
+
+typedef enum { GIRIH_F64 = 0, GIRIH_F32 = 1 } girih_dtype;
+
+typedef enum {
+    GIRIH_NAIVE = 0, /* T launches of one full-domain Jacobi step              */
+    GIRIH_MWD = 1    /* diamond rows: one launch per row of diamond tiles      */
+} girih_algo;
+
+/* Grid descriptor, in elements. */
+typedef struct girih_grid {
+    int64_t nx, ny, nz; /* interior points                      */
+    int32_t halo;       /* must equal the stencil radius         */
+    int64_t pitch_x;    /* >= nx + 2*halo (0 = nx + 2*halo)      */
+    int64_t pitch_y;    /* >= ny + 2*halo (0 = ny + 2*halo)      */
+} girih_grid;
+
+/* Tile parameters (paper, Section "Auto-tuning": diamond width, wavefront
+ * width, threads along x/y/z).  Zero fields are filled with defaults.
+ *  MWD:   diamond_width  Dw, multiple of 2R (of 4 when R = 1);
+ *         wavefront_depth N_F, z-planes per wavefront step (1);
+ *         tile_x         x cells one workgroup owns and stores;
+ *         threads_x      x cells one wave holds per row = 64 * cells per lane
+ *                        (64, 128 or 256);
+ *         threads_y      waves per workgroup (filled in: Dw/2);
+ *         tile_y, tile_z filled in: Dw and nz;
+ *         variant        0 = barrier per wavefront step.
+ *  NAIVE: threads_x, threads_y  block shape (x lanes, y rows);
+ *         tile_z         z planes each thread marches. */
+typedef struct girih_params {
+    int32_t diamond_width;
+    int32_t wavefront_depth;
+    int32_t tile_x;
+    int32_t tile_y;
+    int32_t tile_z;
+    int32_t threads_x;
+    int32_t threads_y;
+    int32_t variant;
+} girih_params;
+
+typedef struct girih_plan_s* girih_plan_t;
+
+/* Create a plan (paper, Section "Auto-tuning": the user selects the stencil
+ * type and grid size).  const_coefs: host array of c0,c1 (7-point constant)
+ * or c0..c4 (25-point constant) in double precision — rounded once to float
+ * for GIRIH_F32 plans; NULL for variable-coefficient stencils.  params: NULL
+ * or a struct whose zero fields take defaults.  Validates everything
+ * (including the on-chip budget of the tile) and allocates nothing on the
+ * device. */
+int girih_plan(girih_plan_t* out, girih_stencil stencil, girih_dtype dtype, const girih_grid* grid,
+               const double* const_coefs, girih_algo algo, const girih_params* params);
+
+/* Run T time steps on the caller's buffers, asynchronously on hip_stream
+ * (a hipStream_t; NULL = default stream).
+ *  buf0: u^0 including its halo.  buf1: same size; its halo is overwritten
+ *  with buf0's, its interior is never read.  Both interiors are clobbered.
+ *  coef_arrays: host array of n_coef DEVICE pointers (7 for 7-point variable,
+ *  13 for 25-point variable, same layout as the field; halos never read), or
+ *  NULL with n_coef = 0.
+ *  On return *result_index = T % 2: the result is the interior of that buffer.
+ *  MWD plans use two plan-owned scratch arrays of the same size, allocated on
+ *  the first run (GIRIH_E_NOMEM if that fails) and freed by girih_destroy. */
+int girih_run(girih_plan_t plan, void* buf0, void* buf1, const void* const* coef_arrays, int32_t n_coef,
+              int64_t T, void* hip_stream, int32_t* result_index);
+
+/* Auto-tuner (paper, Section "Auto-tuning").  Allocates and initialises its
+ * own arrays of the plan's grid (freed before return), times candidates with
+ * HIP events on hip_stream, and writes the best parameters into *best and
+ * the plan.  Test length: multiples of diamond rows, doubled until two
+ * consecutive measurements agree within 3 % or max_seconds is spent.
+ *  mode: GIRIH_TUNE_EXHAUSTIVE  every feasible candidate
+ *        GIRIH_TUNE_HILLCLIMB   per thread shape, local search over Dw and
+ *                               the x tile (the paper's search)
+ *        GIRIH_TUNE_MODEL       only the candidates given by
+ *                               girih_tune_set_candidates (e.g. the top-k of
+ *                               a learned cost model), in that order
+ *  T: steps the tuned run will take (part of the problem).  Each measured
+ *  candidate is appended to the plan's log (girih_tune_log). */
+#define GIRIH_TUNE_EXHAUSTIVE 0
+#define GIRIH_TUNE_HILLCLIMB 1
+#define GIRIH_TUNE_MODEL 2
+int girih_tune(girih_plan_t plan, int32_t mode, int64_t T, double max_seconds, void* hip_stream,
+               girih_params* best, double* best_glups);
+
+/* Candidate list for GIRIH_TUNE_MODEL (copied).  n <= 4096. */
+int girih_tune_set_candidates(girih_plan_t plan, const girih_params* cands, int32_t n);
+
+/* Enumerate the feasible MWD candidates of the plan's problem: writes up to
+ * cap parameter sets into out (may be NULL to count) and their count to *n. */
+int girih_candidates(girih_plan_t plan, girih_params* out, int32_t cap, int32_t* n);
+
+/* One measured tuner candidate. */
+typedef struct girih_tune_record {
+    girih_params params;
+    int64_t lds_bytes;      /* LDS of the candidate's workgroup            */
+    int64_t steps;          /* time steps of the final measurement          */
+    double seconds;         /* time of the final measurement                */
+    double glups;           /* giga lattice updates per second              */
+    int32_t repeats;        /* measurements taken before it was accepted    */
+    int32_t status;         /* 0 = measured, <0 = error code                */
+} girih_tune_record;
+
+/* Copy up to cap records of the plan's tuner log; *n = total count. */
+int girih_tune_log(girih_plan_t plan, girih_tune_record* out, int32_t cap, int32_t* n);
+
+/* Resolved parameters, LDS bytes per workgroup, and the modelled blocked
+ * code balance in bytes per lattice update (paper, Section "Memory traffic
+ * model", scaled to the element size and including the redundant x-halo
+ * reads of the chunking; for NAIVE the streaming (2 + n_coef) * size). */
+int girih_plan_info(girih_plan_t plan, girih_params* params, int64_t* lds_bytes, double* model_bytes_per_lup);
+
+/* Change the parameters of an existing plan (validated like girih_plan). */
+int girih_plan_set_params(girih_plan_t plan, const girih_params* params);
+
+void girih_destroy(girih_plan_t plan);
+
+const char* girih_strerror(int code);
+
+/* Error norms of a result against a reference, accumulated in double
+ * precision over the interior (dtype_a, dtype_b: element types of a and b,
+ * same grid layout): out[0] = sqrt(sum (a-b)^2), out[1] = sqrt(sum b^2),
+ * out[2] = max |a-b|, out[3] = number of bitwise-different elements (only
+ * meaningful when both types are equal).  Synchronises hip_stream. */
+int girih_error_norms(const girih_grid* grid, girih_dtype dtype_a, const void* a, girih_dtype dtype_b,
+                      const void* b, void* hip_stream, double out[4]);
+
+/* Library version string. */
+const char* girih_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GIRIH_H */

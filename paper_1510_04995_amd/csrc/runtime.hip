@@ -1,0 +1,691 @@
+// Host runtime of the library: plans, the diamond-row launcher, the tuner and
+// the C ABI declared in include/girih.h.
+//
+// Runtime (paper, Section "Runtime system"): the paper's runtime hands ready
+// tiles to thread groups through a FIFO queue; a row of diamonds has no
+// internal dependencies and each row depends only on the previous one, so on
+// the GPU one kernel launch per row is the queue: the hardware dispatcher
+// hands the row's workgroups to compute units as they free up, and stream
+// order is the row barrier.
+//
+// Tuner (paper, Section "Auto-tuning"): it allocates its own arrays, times
+// candidates on test runs whose length is a multiple of diamond rows and is
+// doubled until two consecutive runs agree, and searches either every
+// feasible candidate or, per thread shape, by hill climbing over the diamond
+// width and the x tile.  The on-chip capacity bound (the paper prunes with
+// its cache block size model and the user's cache size) is exact here: only
+// compiled kernels whose LDS and registers fit exist in the table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "../../include/girih.h"
+#include "registry.hpp"
+#include "stencils.hpp"
+#include "naive.hpp"
+#include "mwd.hpp"
+
+using namespace girih;
+
+namespace girih {
+
+const std::vector<KernelEntry>& kernel_table() {
+    static const std::vector<KernelEntry> table = [] {
+        std::vector<KernelEntry> t;
+        register_kernels_7c_f64(t);
+        register_kernels_7c_f32(t);
+        register_kernels_7v_f64(t);
+        register_kernels_7v_f32(t);
+        register_kernels_25c_f64(t);
+        register_kernels_25c_f32(t);
+        register_kernels_25v_f64(t);
+        register_kernels_25v_f32(t);
+        return t;
+    }();
+    return table;
+}
+
+}  // namespace girih
+
+namespace {
+
+constexpr int kRadius[4] = {1, 1, 4, 4};
+constexpr int kNCoef[4] = {0, 7, 0, 13};
+constexpr int kNConst[4] = {2, 0, 5, 0};
+
+struct Tuning {
+    std::vector<girih_params> model_cands;
+    std::vector<girih_tune_record> log;
+};
+
+}  // namespace
+
+struct girih_plan_s {
+    int stencil = 0, dtype = 0, algo = 0;
+    girih_grid grid{};
+    double consts[5] = {0, 0, 0, 0, 0};
+    girih_params params{};
+    const KernelEntry* kern = nullptr;   // MWD variant or naive kernel
+    int R = 1;
+    int64_t x_own = 0, n_xchunks = 0;
+    void* scratch[2] = {nullptr, nullptr};
+    size_t scratch_bytes = 0;
+    int scratch_device = -1;
+    Tuning tuning;
+};
+
+namespace {
+
+size_t elem_bytes(int dtype) { return dtype == GIRIH_F64 ? 8 : 4; }
+
+size_t grid_bytes(const girih_plan_s* p) {
+    return (size_t)(p->grid.nz + 2 * p->grid.halo) * (size_t)p->grid.pitch_y * (size_t)p->grid.pitch_x *
+           elem_bytes(p->dtype);
+}
+
+const KernelEntry* find_mwd(int st, int dt, int dw, int vx) {
+    for (const auto& e : kernel_table())
+        if (e.algo == AL_MWD && e.stencil == st && e.dtype == dt && e.dw == dw && e.vx == vx) return &e;
+    return nullptr;
+}
+
+const KernelEntry* find_naive(int st, int dt) {
+    for (const auto& e : kernel_table())
+        if (e.algo == AL_NAIVE && e.stencil == st && e.dtype == dt) return &e;
+    return nullptr;
+}
+
+// Default MWD shape per radius and element size.
+void default_mwd(int R, int dtype, int& dw, int& vx) {
+    if (R == 1) {
+        dw = 8;
+        vx = dtype == GIRIH_F64 ? 2 : 4;
+    } else {
+        dw = 16;
+        vx = 2;
+    }
+}
+
+// Resolve and validate parameters; fills derived fields of the plan.
+int resolve(girih_plan_s* p, const girih_params* in) {
+    girih_params q{};
+    if (in) q = *in;
+    const int R = p->R;
+    if (p->algo == GIRIH_MWD) {
+        int dw = q.diamond_width, vx = q.threads_x ? q.threads_x / 64 : 0;
+        int ddw, dvx;
+        default_mwd(R, p->dtype, ddw, dvx);
+        if (dw == 0) dw = ddw;
+        if (vx == 0) vx = dvx;
+        if (q.threads_x && q.threads_x % 64) return GIRIH_E_INVALID;
+        if (dw <= 0 || dw % (2 * R) || (R == 1 && dw % 4)) return GIRIH_E_INVALID;
+        if (q.wavefront_depth != 0 && q.wavefront_depth != 1) return GIRIH_E_UNSUPPORTED;
+        if (q.variant != 0) return GIRIH_E_UNSUPPORTED;
+        const KernelEntry* k = find_mwd(p->stencil, p->dtype, dw, vx);
+        if (!k) return GIRIH_E_UNSUPPORTED;
+        int64_t xo = q.tile_x ? q.tile_x : k->xown_max;
+        if (xo <= 0) return GIRIH_E_INVALID;
+        if (xo > k->xown_max) return GIRIH_E_LDS;
+        if (xo > p->grid.nx) xo = std::max<int64_t>(1, p->grid.nx);
+        p->kern = k;
+        p->x_own = xo;
+        p->n_xchunks = (p->grid.nx + xo - 1) / xo;
+        q.diamond_width = dw;
+        q.wavefront_depth = 1;
+        q.tile_x = (int32_t)xo;
+        q.tile_y = dw;
+        q.tile_z = (int32_t)std::min<int64_t>(p->grid.nz, INT32_MAX);
+        q.threads_x = 64 * vx;
+        q.threads_y = dw / 2;
+        q.variant = 0;
+    } else {
+        if (q.threads_x == 0) q.threads_x = 64;
+        if (q.threads_y == 0) q.threads_y = 4;
+        if (q.tile_z == 0) q.tile_z = 64;
+        if (q.threads_x <= 0 || q.threads_y <= 0 || q.tile_z <= 0) return GIRIH_E_INVALID;
+        if (q.threads_x * q.threads_y > 256 || q.threads_x % 64) return GIRIH_E_INVALID;
+        p->kern = find_naive(p->stencil, p->dtype);
+        if (!p->kern) return GIRIH_E_UNSUPPORTED;
+        q.diamond_width = 0;
+        q.wavefront_depth = 0;
+        q.tile_x = q.threads_x;
+        q.tile_y = q.threads_y;
+        q.variant = 0;
+    }
+    p->params = q;
+    return GIRIH_OK;
+}
+
+template <typename Real>
+void fill_coefs(const girih_plan_s* p, const void* const* arrays, CoefArgs<Real>& c) {
+    for (int m = 0; m < 13; ++m) c.arr[m] = nullptr;
+    for (int m = 0; m < 5; ++m) c.k[m] = (Real)p->consts[m];
+    for (int m = 0; m < kNCoef[p->stencil]; ++m) c.arr[m] = static_cast<const Real*>(arrays[m]);
+}
+
+GridDesc desc_of(const girih_plan_s* p) {
+    GridDesc g;
+    g.nx = p->grid.nx;
+    g.ny = p->grid.ny;
+    g.nz = p->grid.nz;
+    g.pitch_x = p->grid.pitch_x;
+    g.pitch_y = p->grid.pitch_y;
+    g.h = p->grid.halo;
+    return g;
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) return GIRIH_E_HIP;  \
+    } while (0)
+
+template <typename Real>
+int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s) {
+    NaiveArgs<Real> a;
+    a.g = desc_of(p);
+    fill_coefs<Real>(p, coefs, a.coef);
+    a.z_chunk = p->params.tile_z;
+    const dim3 block(p->params.threads_x, p->params.threads_y);
+    const dim3 grid((unsigned)((p->grid.nx + block.x - 1) / block.x), (unsigned)((p->grid.ny + block.y - 1) / block.y),
+                    (unsigned)((p->grid.nz + a.z_chunk - 1) / a.z_chunk));
+    Real* b[2] = {static_cast<Real*>(buf0), static_cast<Real*>(buf1)};
+    for (int64_t t = 0; t < T; ++t) {
+        a.V = b[t & 1];
+        a.U = b[(t + 1) & 1];
+        HIPCHK(p->kern->launch(&a, grid, block, s));
+    }
+    return GIRIH_OK;
+}
+
+int ensure_scratch(girih_plan_s* p) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const size_t need = grid_bytes(p);
+    if (p->scratch[0] && p->scratch_bytes == need && p->scratch_device == dev) return GIRIH_OK;
+    for (int i = 0; i < 2; ++i) {
+        if (p->scratch[i]) (void)hipFree(p->scratch[i]);
+        p->scratch[i] = nullptr;
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (hipMalloc(&p->scratch[i], need) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < 2; ++j) {
+                if (p->scratch[j]) (void)hipFree(p->scratch[j]);
+                p->scratch[j] = nullptr;
+            }
+            return GIRIH_E_NOMEM;
+        }
+    }
+    p->scratch_bytes = need;
+    p->scratch_device = dev;
+    return GIRIH_OK;
+}
+
+template <typename Real>
+int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s) {
+    int rc = ensure_scratch(p);
+    if (rc) return rc;
+    const int64_t nx = p->grid.nx, ny = p->grid.ny, nz = p->grid.nz, h = p->grid.halo;
+    const int64_t px = p->grid.pitch_x, py = p->grid.pitch_y;
+    const int eb = (int)sizeof(Real);
+    // every array carries buf0's fixed halo
+    HIPCHK(launch_copy_halo(buf0, p->scratch[0], eb, nx, ny, nz, h, px, py, s));
+    HIPCHK(launch_copy_halo(buf0, p->scratch[1], eb, nx, ny, nz, h, px, py, s));
+    const int dw = p->kern->dw;
+    const int64_t H = dw / (2 * p->R);
+    const int64_t n_rows = (T - 1) / H + 2;
+    Real* user[2] = {static_cast<Real*>(buf0), static_cast<Real*>(buf1)};
+    Real* scr[2] = {static_cast<Real*>(p->scratch[0]), static_cast<Real*>(p->scratch[1])};
+    // The last row must write the caller's pair: rows alternate in -> out, so
+    // row 0 reads the caller's pair iff the row count is even; otherwise u^0
+    // is first copied into the scratch pair.
+    bool in_user = (n_rows % 2) == 0;
+    if (!in_user) HIPCHK(hipMemcpyAsync(scr[0], user[0], grid_bytes(p), hipMemcpyDeviceToDevice, s));
+    MwdArgs<Real> a;
+    a.g = desc_of(p);
+    fill_coefs<Real>(p, coefs, a.coef);
+    a.T = T;
+    a.x_own = (int32_t)p->x_own;
+    const dim3 block(p->kern->nthreads);
+    for (int64_t r = 0; r < n_rows; ++r) {
+        Real** in = in_user ? user : scr;
+        Real** out = in_user ? scr : user;
+        a.in[0] = in[0];
+        a.in[1] = in[1];
+        a.out[0] = out[0];
+        a.out[1] = out[1];
+        a.t_c = r * H;
+        const int64_t off = (r & 1) ? dw / 2 : 0;
+        a.c_first = off;
+        const int64_t n_diamonds = (ny + dw / 2 - off + dw - 1) / dw;
+        const dim3 grid((unsigned)p->n_xchunks, (unsigned)n_diamonds);
+        HIPCHK(p->kern->launch(&a, grid, block, s));
+        in_user = !in_user;
+    }
+    return GIRIH_OK;
+}
+
+int validate_grid(const girih_grid* g, int R, girih_grid& out) {
+    if (!g) return GIRIH_E_INVALID;
+    out = *g;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->halo != R) return GIRIH_E_INVALID;
+    if (out.pitch_x == 0) out.pitch_x = g->nx + 2 * R;
+    if (out.pitch_y == 0) out.pitch_y = g->ny + 2 * R;
+    if (out.pitch_x < g->nx + 2 * R || out.pitch_y < g->ny + 2 * R) return GIRIH_E_INVALID;
+    // kernel grid dimensions: y of the haloed box and diamonds per row fit 16 bits of gridDim
+    if (g->ny + 2 * R > 65535 || g->nz + 2 * R > 65535) return GIRIH_E_UNSUPPORTED;
+    return GIRIH_OK;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ tuner
+
+struct TuneBufs {
+    void* f[2] = {nullptr, nullptr};
+    std::vector<void*> coef;
+    ~TuneBufs() {
+        for (void* q : f)
+            if (q) (void)hipFree(q);
+        for (void* q : coef)
+            if (q) (void)hipFree(q);
+    }
+};
+
+template <typename Real>
+__global__ void tune_fill_kernel(Real* __restrict__ a, int64_t n, Real v, uint32_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        // cheap hash in [0.5, 1.5) * v : keeps values normal and bounded
+        uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+        x ^= x >> 15;
+        x *= 2246822519u;
+        x ^= x >> 13;
+        a[i] = v * (Real)(0.5 + (double)(x & 0xffffff) / 16777216.0);
+    }
+}
+
+int alloc_tune_bufs(girih_plan_s* p, TuneBufs& b, hipStream_t s) {
+    const size_t bytes = grid_bytes(p);
+    const int64_t n = (int64_t)(bytes / elem_bytes(p->dtype));
+    const int nc = kNCoef[p->stencil];
+    b.coef.assign(nc, nullptr);
+    for (int i = 0; i < 2; ++i)
+        if (hipMalloc(&b.f[i], bytes) != hipSuccess) { (void)hipGetLastError(); return GIRIH_E_NOMEM; }
+    for (int i = 0; i < nc; ++i)
+        if (hipMalloc(&b.coef[i], bytes) != hipSuccess) { (void)hipGetLastError(); return GIRIH_E_NOMEM; }
+    const double cw = nc ? 1.0 / (nc == 7 ? 7.0 : 25.0) : 0.0;
+    for (int i = 0; i < 2 + nc; ++i) {
+        void* q = i < 2 ? b.f[i] : b.coef[i - 2];
+        const double v = i < 2 ? 1.0 : cw;
+        if (p->dtype == GIRIH_F64)
+            hipLaunchKernelGGL(tune_fill_kernel<double>, dim3(4096), dim3(256), 0, s, (double*)q, n, v, 17u * i + 1);
+        else
+            hipLaunchKernelGGL(tune_fill_kernel<float>, dim3(4096), dim3(256), 0, s, (float*)q, n, (float)v, 17u * i + 1);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return GIRIH_OK;
+}
+
+int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s);
+
+// Time one candidate: runs of k diamond rows (k*H steps for MWD, k*8 steps
+// naive), k doubling until two consecutive rates agree within 3 %.
+int measure(girih_plan_s* p, TuneBufs& b, hipStream_t s, double max_seconds, girih_tune_record& rec) {
+    const int64_t H = p->algo == GIRIH_MWD ? p->params.diamond_width / (2 * p->R) : 8;
+    const double lups_per_step = (double)p->grid.nx * p->grid.ny * p->grid.nz;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const void* const* coefs = b.coef.empty() ? nullptr : (const void* const*)b.coef.data();
+    // warm-up (also allocates the scratch pair)
+    int rc = run_any(p, b.f[0], b.f[1], coefs, H, s);
+    if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
+    double prev = -1, rate = 0, secs = 0;
+    int64_t rows = 2, steps = 0;
+    int reps = 0;
+    const double t0 = now_s();
+    for (;;) {
+        steps = rows * H;
+        HIPCHK(hipEventRecord(e0, s));
+        rc = run_any(p, b.f[0], b.f[1], coefs, steps, s);
+        if (rc) break;
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        secs = ms * 1e-3;
+        rate = lups_per_step * steps / secs * 1e-9;
+        ++reps;
+        if (prev > 0 && std::fabs(rate - prev) <= 0.03 * std::max(rate, prev)) break;
+        if (now_s() - t0 > max_seconds || reps >= 12) break;
+        prev = rate;
+        if (secs < 0.05) rows *= 2;   // grow until a run is long enough to be stable
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    rec.params = p->params;
+    rec.lds_bytes = p->kern->lds_bytes;
+    rec.steps = steps;
+    rec.seconds = secs;
+    rec.glups = rate;
+    rec.repeats = reps;
+    rec.status = rc;
+    return rc;
+}
+
+std::vector<girih_params> mwd_candidates(const girih_plan_s* p) {
+    std::vector<girih_params> out;
+    for (const auto& e : kernel_table()) {
+        if (e.algo != AL_MWD || e.stencil != p->stencil || e.dtype != p->dtype) continue;
+        if (e.xown_max < 8) continue;
+        // x tiles: the widest, and the widths that split nx into 1-3 more chunks
+        std::set<int64_t> tiles;
+        const int64_t nx = p->grid.nx;
+        const int64_t c0 = (nx + e.xown_max - 1) / e.xown_max;
+        for (int64_t c = c0; c <= c0 + 3; ++c) {
+            const int64_t t = (nx + c - 1) / c;
+            if (t >= 8 && t <= e.xown_max) tiles.insert(t);
+        }
+        for (int64_t t : tiles) {
+            girih_params q{};
+            q.diamond_width = e.dw;
+            q.wavefront_depth = 1;
+            q.tile_x = (int32_t)t;
+            q.threads_x = 64 * e.vx;
+            q.threads_y = e.dw / 2;
+            out.push_back(q);
+        }
+    }
+    return out;
+}
+
+std::vector<girih_params> naive_candidates(const girih_plan_s*) {
+    std::vector<girih_params> out;
+    const int tx[] = {64, 128, 256};
+    const int ty[] = {1, 2, 4};
+    const int tz[] = {16, 64, 256};
+    for (int a : tx)
+        for (int b : ty)
+            for (int c : tz) {
+                if (a * b > 256) continue;
+                girih_params q{};
+                q.threads_x = a;
+                q.threads_y = b;
+                q.tile_z = c;
+                out.push_back(q);
+            }
+    return out;
+}
+
+}  // namespace
+
+namespace {
+int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s) {
+    if (T == 0) return GIRIH_OK;
+    HIPCHK(launch_copy_halo(b0, b1, (int)elem_bytes(p->dtype), p->grid.nx, p->grid.ny, p->grid.nz, p->grid.halo,
+                            p->grid.pitch_x, p->grid.pitch_y, s));
+    if (p->algo == GIRIH_NAIVE)
+        return p->dtype == GIRIH_F64 ? run_naive<double>(p, b0, b1, coefs, T, s)
+                                     : run_naive<float>(p, b0, b1, coefs, T, s);
+    return p->dtype == GIRIH_F64 ? run_mwd<double>(p, b0, b1, coefs, T, s) : run_mwd<float>(p, b0, b1, coefs, T, s);
+}
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int girih_plan(girih_plan_t* out, girih_stencil stencil, girih_dtype dtype, const girih_grid* grid,
+               const double* const_coefs, girih_algo algo, const girih_params* params) {
+    if (!out) return GIRIH_E_INVALID;
+    *out = nullptr;
+    if ((int)stencil < 0 || (int)stencil > 3 || (dtype != GIRIH_F64 && dtype != GIRIH_F32) ||
+        (algo != GIRIH_NAIVE && algo != GIRIH_MWD))
+        return GIRIH_E_INVALID;
+    girih_grid g;
+    int rc = validate_grid(grid, kRadius[stencil], g);
+    if (rc) return rc;
+    if (kNConst[stencil] && !const_coefs) return GIRIH_E_INVALID;
+    girih_plan_s* p = new (std::nothrow) girih_plan_s();
+    if (!p) return GIRIH_E_NOMEM;
+    p->stencil = stencil;
+    p->dtype = dtype;
+    p->algo = algo;
+    p->grid = g;
+    p->R = kRadius[stencil];
+    for (int m = 0; m < kNConst[stencil]; ++m) {
+        const double c = const_coefs[m];
+        if (!std::isfinite(c)) { delete p; return GIRIH_E_INVALID; }
+        p->consts[m] = dtype == GIRIH_F32 ? (double)(float)c : c;
+    }
+    rc = resolve(p, params);
+    if (rc) { delete p; return rc; }
+    *out = p;
+    return GIRIH_OK;
+}
+
+int girih_plan_set_params(girih_plan_t p, const girih_params* params) {
+    if (!p) return GIRIH_E_INVALID;
+    girih_plan_s tmp = *p;
+    tmp.scratch[0] = tmp.scratch[1] = nullptr;   // not owned by the copy
+    int rc = resolve(&tmp, params);
+    if (rc) return rc;
+    p->params = tmp.params;
+    p->kern = tmp.kern;
+    p->x_own = tmp.x_own;
+    p->n_xchunks = tmp.n_xchunks;
+    return GIRIH_OK;
+}
+
+int girih_run(girih_plan_t p, void* buf0, void* buf1, const void* const* coef_arrays, int32_t n_coef, int64_t T,
+              void* hip_stream, int32_t* result_index) {
+    if (!p || !buf0 || !buf1 || buf0 == buf1 || T < 0) return GIRIH_E_INVALID;
+    if (n_coef != kNCoef[p->stencil]) return GIRIH_E_INVALID;
+    if (n_coef && !coef_arrays) return GIRIH_E_INVALID;
+    for (int m = 0; m < n_coef; ++m)
+        if (!coef_arrays[m]) return GIRIH_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int rc = run_any(p, buf0, buf1, coef_arrays, T, s);
+    if (rc) return rc;
+    if (result_index) *result_index = (int32_t)(T & 1);
+    return GIRIH_OK;
+}
+
+int girih_tune_set_candidates(girih_plan_t p, const girih_params* cands, int32_t n) {
+    if (!p || n < 0 || n > 4096 || (n && !cands)) return GIRIH_E_INVALID;
+    p->tuning.model_cands.assign(cands, cands + n);
+    return GIRIH_OK;
+}
+
+int girih_candidates(girih_plan_t p, girih_params* out, int32_t cap, int32_t* n) {
+    if (!p || !n || cap < 0) return GIRIH_E_INVALID;
+    auto c = p->algo == GIRIH_MWD ? mwd_candidates(p) : naive_candidates(p);
+    *n = (int32_t)c.size();
+    if (out)
+        for (int32_t i = 0; i < cap && i < (int32_t)c.size(); ++i) out[i] = c[i];
+    return GIRIH_OK;
+}
+
+int girih_tune(girih_plan_t p, int32_t mode, int64_t T, double max_seconds, void* hip_stream, girih_params* best,
+               double* best_glups) {
+    if (!p || T < 0 || !(max_seconds > 0)) return GIRIH_E_INVALID;
+    if (mode < 0 || mode > 2) return GIRIH_E_INVALID;
+    (void)T;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<girih_params> cands;
+    if (mode == GIRIH_TUNE_MODEL) cands = p->tuning.model_cands;
+    else cands = p->algo == GIRIH_MWD ? mwd_candidates(p) : naive_candidates(p);
+    if (cands.empty()) return GIRIH_E_UNSUPPORTED;
+    const girih_params saved = p->params;
+    TuneBufs bufs;
+    int rc = alloc_tune_bufs(p, bufs, s);
+    if (rc) return rc;
+    const double t_start = now_s();
+    const double per_cand = std::max(0.05, std::min(2.0, max_seconds / std::max<size_t>(cands.size(), 1)));
+    std::map<std::vector<int32_t>, double> seen;
+    auto key = [](const girih_params& q) {
+        return std::vector<int32_t>{q.diamond_width, q.tile_x, q.threads_x, q.threads_y, q.tile_z};
+    };
+    double best_rate = -1;
+    girih_params best_p = saved;
+    auto eval = [&](const girih_params& q) -> double {
+        auto it = seen.find(key(q));
+        if (it != seen.end()) return it->second;
+        girih_tune_record rec{};
+        rec.params = q;
+        int r2 = girih_plan_set_params(p, &q);
+        if (r2 == GIRIH_OK) r2 = measure(p, bufs, s, per_cand, rec);
+        rec.status = r2;
+        if (r2 != GIRIH_OK) {
+            (void)hipGetLastError();
+            rec.glups = 0;
+        }
+        p->tuning.log.push_back(rec);
+        seen[key(q)] = rec.glups;
+        if (rec.glups > best_rate) {
+            best_rate = rec.glups;
+            best_p = p->params;
+        }
+        return rec.glups;
+    };
+    if (mode == GIRIH_TUNE_HILLCLIMB && p->algo == GIRIH_MWD) {
+        // per thread shape (cells per lane), local search over (Dw, x tile)
+        std::map<int, std::vector<girih_params>> by_shape;
+        for (const auto& q : cands) by_shape[q.threads_x].push_back(q);
+        for (auto& kv : by_shape) {
+            auto& v = kv.second;
+            std::vector<int> dws;
+            for (auto& q : v) dws.push_back(q.diamond_width);
+            std::sort(dws.begin(), dws.end());
+            dws.erase(std::unique(dws.begin(), dws.end()), dws.end());
+            auto tiles_of = [&](int dw) {
+                std::vector<int> t;
+                for (auto& q : v)
+                    if (q.diamond_width == dw) t.push_back(q.tile_x);
+                std::sort(t.begin(), t.end());
+                return t;
+            };
+            auto make = [&](int dw, int tx) {
+                for (auto& q : v)
+                    if (q.diamond_width == dw && q.tile_x == tx) return q;
+                return v[0];
+            };
+            // start: median diamond width, widest tile
+            int di = (int)dws.size() / 2;
+            auto ts = tiles_of(dws[di]);
+            int ti = (int)ts.size() - 1;
+            double cur = eval(make(dws[di], ts[ti]));
+            for (int guard = 0; guard < 64 && now_s() - t_start < max_seconds; ++guard) {
+                int bd = di, bt = ti;
+                double bv = cur;
+                const int moves[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+                for (auto& m : moves) {
+                    const int nd = di + m[0];
+                    if (nd < 0 || nd >= (int)dws.size()) continue;
+                    auto nts = tiles_of(dws[nd]);
+                    int nt = m[0] ? (int)nts.size() - 1 : ti + m[1];
+                    if (nt < 0 || nt >= (int)nts.size()) continue;
+                    const double r = eval(make(dws[nd], nts[nt]));
+                    if (r > bv) { bv = r; bd = nd; bt = nt; }
+                }
+                if (bd == di && bt == ti) break;
+                di = bd;
+                ti = bt;
+                cur = bv;
+            }
+        }
+    } else {
+        for (const auto& q : cands) {
+            if (now_s() - t_start > max_seconds && best_rate > 0) break;
+            eval(q);
+        }
+    }
+    if (best_rate <= 0) {
+        (void)girih_plan_set_params(p, &saved);
+        return GIRIH_E_UNSUPPORTED;
+    }
+    rc = girih_plan_set_params(p, &best_p);
+    if (rc) return rc;
+    if (best) *best = p->params;
+    if (best_glups) *best_glups = best_rate;
+    return GIRIH_OK;
+}
+
+int girih_tune_log(girih_plan_t p, girih_tune_record* out, int32_t cap, int32_t* n) {
+    if (!p || !n || cap < 0) return GIRIH_E_INVALID;
+    *n = (int32_t)p->tuning.log.size();
+    if (out)
+        for (int32_t i = 0; i < cap && i < *n; ++i) out[i] = p->tuning.log[i];
+    return GIRIH_OK;
+}
+
+int girih_plan_info(girih_plan_t p, girih_params* params, int64_t* lds_bytes, double* model_bytes_per_lup) {
+    if (!p) return GIRIH_E_INVALID;
+    if (params) *params = p->params;
+    if (lds_bytes) *lds_bytes = p->kern ? p->kern->lds_bytes : 0;
+    if (model_bytes_per_lup) {
+        const double s = (double)elem_bytes(p->dtype);
+        const int ND = 2 + kNCoef[p->stencil];
+        if (p->algo == GIRIH_NAIVE) {
+            *model_bytes_per_lup = ND * s;
+        } else {
+            // paper's B_C in words: R*[(2Dw-2R) + (N_D*Dw+2R)] * 2 / Dw^2, the read
+            // term widened by the redundant x-halo of the chunk
+            const double Dw = p->params.diamond_width, R = p->R;
+            const double L = Dw / R, hx = R * (L - 1);
+            const double rho = ((double)p->x_own + 2 * hx) / (double)p->x_own;
+            *model_bytes_per_lup = 2 * s * R * ((2 * Dw - 2 * R) + rho * (ND * Dw + 2 * R)) / (Dw * Dw);
+        }
+    }
+    return GIRIH_OK;
+}
+
+void girih_destroy(girih_plan_t p) {
+    if (!p) return;
+    for (int i = 0; i < 2; ++i)
+        if (p->scratch[i]) (void)hipFree(p->scratch[i]);
+    delete p;
+}
+
+const char* girih_strerror(int code) {
+    switch (code) {
+        case GIRIH_OK: return "ok";
+        case GIRIH_E_INVALID: return "invalid argument";
+        case GIRIH_E_UNSUPPORTED: return "unsupported combination (no compiled kernel)";
+        case GIRIH_E_LDS: return "tile exceeds the on-chip budget of the kernel";
+        case GIRIH_E_HIP: return "HIP runtime error";
+        case GIRIH_E_NOMEM: return "allocation failed";
+        case GIRIH_E_NOGPU: return "no usable GPU";
+        default: return "unknown error";
+    }
+}
+
+int girih_error_norms(const girih_grid* grid, girih_dtype dta, const void* a, girih_dtype dtb, const void* b,
+                      void* hip_stream, double out[4]) {
+    if (!grid || !a || !b || !out) return GIRIH_E_INVALID;
+    if ((dta != GIRIH_F64 && dta != GIRIH_F32) || (dtb != GIRIH_F64 && dtb != GIRIH_F32)) return GIRIH_E_INVALID;
+    const int64_t h = grid->halo;
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || h < 0) return GIRIH_E_INVALID;
+    const int64_t px = grid->pitch_x ? grid->pitch_x : grid->nx + 2 * h;
+    const int64_t py = grid->pitch_y ? grid->pitch_y : grid->ny + 2 * h;
+    if (px < grid->nx + 2 * h || py < grid->ny + 2 * h) return GIRIH_E_INVALID;
+    if (error_norms(a, dta, b, dtb, grid->nx, grid->ny, grid->nz, h, px, py, static_cast<hipStream_t>(hip_stream),
+                    out) != hipSuccess)
+        return GIRIH_E_HIP;
+    return GIRIH_OK;
+}
+
+const char* girih_version(void) { return "girih-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+"""ctypes binding of ``libgirih.so`` (declared in ``include/girih.h``).
+
+Argument marshalling only: every step of the sweep runs in the library's HIP
+kernels.  Device memory and streams come from PyTorch (``tensor.data_ptr()``,
+``torch.cuda.current_stream().cuda_stream``).  If the library is missing this
+module raises on first use — there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgirih.so")
+
+OK = 0
+E_INVALID, E_UNSUPPORTED, E_LDS, E_HIP, E_NOMEM, E_NOGPU = -1, -2, -3, -4, -5, -6
+
+STENCIL_IDS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3}
+DTYPE_IDS = {"f64": 0, "f32": 1}
+ALGO_IDS = {"naive": 0, "mwd": 1}
+TUNE_MODES = {"exhaustive": 0, "hillclimb": 1, "model": 2}
+RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4}
+N_COEF = {"7c": 0, "7v": 7, "25c": 0, "25v": 13}
+
+
+class GirihGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("halo", ctypes.c_int32), ("pitch_x", ctypes.c_int64), ("pitch_y", ctypes.c_int64)]
+
+
+class GirihParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("diamond_width", "wavefront_depth", "tile_x", "tile_y",
+                                                "tile_z", "threads_x", "threads_y", "variant")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        p = cls()
+        for n, _ in cls._fields_:
+            setattr(p, n, int(d.get(n, 0) or 0))
+        return p
+
+
+class GirihTuneRecord(ctypes.Structure):
+    _fields_ = [("params", GirihParams), ("lds_bytes", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("glups", ctypes.c_double), ("repeats", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+
+class GirihError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, _lib().girih_strerror(code).decode(), code))
+
+
+_LIB = None
+
+# name -> (restype, argtypes): the exported symbols of include/girih.h
+SIGNATURES = {
+    "girih_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(GirihGrid), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                  ctypes.POINTER(GirihParams)]),
+    "girih_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "girih_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.POINTER(ctypes.c_double)]),
+    "girih_tune_set_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.c_int32]),
+    "girih_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "girih_tune_log": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihTuneRecord), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "girih_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "girih_plan_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams)]),
+    "girih_destroy": (None, [ctypes.c_void_p]),
+    "girih_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "girih_error_norms": (ctypes.c_int, [ctypes.POINTER(GirihGrid), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "girih_version": (ctypes.c_char_p, []),
+}
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgirih.so is not built (run __graft_entry__.build() or "
+                               "python paper_1510_04995_amd/build.py)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise GirihError(rc, what)
+
+
+def make_grid(nx, ny, nz, halo, pitch_x=0, pitch_y=0):
+    return GirihGrid(int(nx), int(ny), int(nz), int(halo), int(pitch_x), int(pitch_y))
+
+
+# ---- thin wrappers with the C names -------------------------------------------
+
+def girih_plan(stencil, dtype, grid, const_coefs=None, algo="mwd", params=None):
+    out = ctypes.c_void_p()
+    cc = None
+    if const_coefs is not None:
+        vals = [float(c) for c in const_coefs]
+        cc = (ctypes.c_double * len(vals))(*vals)
+    p = None
+    if params is not None:
+        p = params if isinstance(params, GirihParams) else GirihParams.from_dict(params)
+    rc = _lib().girih_plan(ctypes.byref(out), STENCIL_IDS[stencil], DTYPE_IDS[dtype], ctypes.byref(grid),
+                           cc, ALGO_IDS[algo], ctypes.byref(p) if p is not None else None)
+    _check(rc, "girih_plan")
+    return out
+
+
+def girih_run(plan, buf0_ptr, buf1_ptr, coef_ptrs, T, stream_ptr):
+    n = len(coef_ptrs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[ctypes.c_void_p(int(q)) for q in coef_ptrs]) if n else None
+    res = ctypes.c_int32(-1)
+    rc = _lib().girih_run(plan, ctypes.c_void_p(int(buf0_ptr)), ctypes.c_void_p(int(buf1_ptr)),
+                          ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)) if n else None, n, int(T),
+                          ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None, ctypes.byref(res))
+    _check(rc, "girih_run")
+    return res.value
+
+
+def girih_tune(plan, mode, T, max_seconds, stream_ptr):
+    best = GirihParams()
+    g = ctypes.c_double(0)
+    rc = _lib().girih_tune(plan, TUNE_MODES[mode] if isinstance(mode, str) else int(mode), int(T),
+                           float(max_seconds), ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None,
+                           ctypes.byref(best), ctypes.byref(g))
+    _check(rc, "girih_tune")
+    return best.as_dict(), g.value
+
+
+def girih_tune_set_candidates(plan, cands):
+    arr = (GirihParams * max(len(cands), 1))(*[c if isinstance(c, GirihParams) else GirihParams.from_dict(c)
+                                               for c in cands])
+    _check(_lib().girih_tune_set_candidates(plan, arr, len(cands)), "girih_tune_set_candidates")
+
+
+def girih_candidates(plan):
+    n = ctypes.c_int32(0)
+    _check(_lib().girih_candidates(plan, None, 0, ctypes.byref(n)), "girih_candidates")
+    arr = (GirihParams * max(n.value, 1))()
+    _check(_lib().girih_candidates(plan, arr, n.value, ctypes.byref(n)), "girih_candidates")
+    return [arr[i].as_dict() for i in range(n.value)]
+
+
+def girih_tune_log(plan):
+    n = ctypes.c_int32(0)
+    _check(_lib().girih_tune_log(plan, None, 0, ctypes.byref(n)), "girih_tune_log")
+    arr = (GirihTuneRecord * max(n.value, 1))()
+    _check(_lib().girih_tune_log(plan, arr, n.value, ctypes.byref(n)), "girih_tune_log")
+    out = []
+    for i in range(n.value):
+        r = arr[i]
+        out.append(dict(params=r.params.as_dict(), lds_bytes=r.lds_bytes, steps=r.steps, seconds=r.seconds,
+                        glups=r.glups, repeats=r.repeats, status=r.status))
+    return out
+
+
+def girih_plan_info(plan):
+    p = GirihParams()
+    lds = ctypes.c_int64(0)
+    bpl = ctypes.c_double(0)
+    _check(_lib().girih_plan_info(plan, ctypes.byref(p), ctypes.byref(lds), ctypes.byref(bpl)), "girih_plan_info")
+    return p.as_dict(), lds.value, bpl.value
+
+
+def girih_plan_set_params(plan, params):
+    p = params if isinstance(params, GirihParams) else GirihParams.from_dict(params)
+    _check(_lib().girih_plan_set_params(plan, ctypes.byref(p)), "girih_plan_set_params")
+
+
+def girih_destroy(plan):
+    _lib().girih_destroy(plan)
+
+
+def girih_strerror(code):
+    return _lib().girih_strerror(int(code)).decode()
+
+
+def girih_error_norms(grid, dtype_a, a_ptr, dtype_b, b_ptr, stream_ptr):
+    out = (ctypes.c_double * 4)()
+    rc = _lib().girih_error_norms(ctypes.byref(grid), DTYPE_IDS[dtype_a], ctypes.c_void_p(int(a_ptr)),
+                                  DTYPE_IDS[dtype_b], ctypes.c_void_p(int(b_ptr)),
+                                  ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None, out)
+    _check(rc, "girih_error_norms")
+    return list(out)
+
+
+def girih_version():
+    return _lib().girih_version().decode()

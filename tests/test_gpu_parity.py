@@ -1,0 +1,160 @@
+"""GPU parity: the HIP naive sweep and the HIP diamond/wavefront (MWD) sweep
+against the CPU oracle, element by element, through the C ABI.
+
+Bar (from the method: blocking only reorders point updates, every kernel
+evaluates the listings' order without contraction):
+  * naive GPU == oracle, bit for bit (float64 and float32 oracles);
+  * MWD GPU == naive GPU == oracle, bit for bit;
+  * float64 MWD within 1e-12 relative L2 of the float64 oracle (implied).
+Sizes span several x-chunks, several diamonds and rows, ragged tails in every
+axis, T below, at and above the diamond height, and the degenerate cases
+(T = 0, T = 1, grids thinner than a diamond).  The second buffer's interior is
+poisoned with NaN: a schedule that reads a value it did not produce fails.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_util import inputs, oracle_run, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_bitwise(a, b, what):
+    if not np.array_equal(a, b):
+        bad = np.argwhere(~((a == b) | (np.isnan(a) & np.isnan(b))))
+        raise AssertionError("%s: %d elements differ, first at %s: %r vs %r"
+                             % (what, len(bad), bad[:3].tolist(), a[tuple(bad[0])], b[tuple(bad[0])]))
+
+
+CASES_NAIVE = [("7c", (37, 29, 23), 5), ("7v", (35, 19, 21), 4), ("25c", (45, 37, 29), 3), ("25v", (41, 35, 33), 2)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("stencil,n,T", CASES_NAIVE)
+def test_naive_matches_oracle_bitwise(stencil, n, T, dtype):
+    u0, c, arr = inputs(stencil, *n, seed=1)
+    print("naive", stencil, dtype, n, T, flush=True)
+    got, _ = run_gpu(stencil, dtype, u0, c, arr, T, algo="naive")
+    ref = oracle_run(stencil, u0, c, arr, T, dtype)
+    assert_bitwise(got, ref, "naive %s %s" % (stencil, dtype))
+
+
+def test_naive_block_shapes():
+    u0, c, arr = inputs("7c", 70, 33, 41, seed=2)
+    ref = oracle_run("7c", u0, c, arr, 3)
+    for p in ({"threads_x": 128, "threads_y": 2, "tile_z": 7}, {"threads_x": 64, "threads_y": 1, "tile_z": 200},
+              {"threads_x": 256, "threads_y": 1, "tile_z": 16}):
+        got, _ = run_gpu("7c", "f64", u0, c, arr, 3, algo="naive", params=p)
+        assert_bitwise(got, ref, "naive %s" % p)
+
+
+# (stencil, dtype, Dw, cells per lane, tile_x or 0, grid (nx, ny, nz), list of T)
+MWD_CASES = [
+    ("7c", "f64", 4, 1, 0, (61, 23, 17), [1, 2, 3, 5, 8]),
+    ("7c", "f64", 8, 2, 0, (150, 45, 19), [1, 4, 5, 9, 13]),
+    ("7c", "f64", 8, 2, 40, (150, 45, 19), [7]),
+    ("7c", "f64", 12, 2, 0, (131, 50, 12), [6, 7, 16]),
+    ("7c", "f64", 16, 1, 0, (70, 70, 9), [3, 8, 17]),
+    ("7c", "f64", 16, 2, 0, (200, 40, 11), [9, 16]),
+    ("7c", "f32", 8, 4, 0, (300, 33, 15), [5, 12]),
+    ("7c", "f32", 16, 4, 0, (260, 37, 9), [10]),
+    ("7v", "f64", 8, 2, 0, (129, 30, 14), [3, 7]),
+    ("7v", "f32", 12, 2, 0, (120, 41, 10), [6, 11]),
+    ("25c", "f64", 8, 2, 0, (140, 30, 20), [1, 2, 3]),
+    ("25c", "f64", 16, 2, 0, (150, 50, 22), [2, 3, 5]),
+    ("25c", "f32", 16, 4, 0, (260, 45, 17), [4]),
+    ("25c", "f64", 24, 2, 0, (100, 60, 21), [3, 7]),
+    ("25v", "f64", 16, 2, 0, (130, 40, 19), [2, 5]),
+    ("25v", "f32", 8, 4, 0, (250, 26, 18), [3]),
+]
+
+
+@pytest.mark.parametrize("stencil,dtype,dw,vx,tx,n,Ts", MWD_CASES)
+def test_mwd_matches_naive_and_oracle_bitwise(stencil, dtype, dw, vx, tx, n, Ts):
+    u0, c, arr = inputs(stencil, *n, seed=3)
+    params = {"diamond_width": dw, "threads_x": 64 * vx, "tile_x": tx}
+    for T in Ts:
+        print("mwd", stencil, dtype, dw, vx, tx, n, T, flush=True)
+        got, info = run_gpu(stencil, dtype, u0, c, arr, T, algo="mwd", params=params)
+        assert info["params"]["diamond_width"] == dw
+        ref = oracle_run(stencil, u0, c, arr, T, dtype)
+        assert_bitwise(got, ref, "mwd %s %s Dw=%d vx=%d T=%d" % (stencil, dtype, dw, vx, T))
+        naive, _ = run_gpu(stencil, dtype, u0, c, arr, T, algo="naive")
+        assert_bitwise(got, naive, "mwd vs naive")
+        if dtype == "f64":
+            assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_mwd_T0_and_T1_and_tiny_grids():
+    for n in ((1, 1, 1), (3, 2, 5), (9, 1, 4), (2, 17, 1)):
+        u0, c, arr = inputs("7c", *n, seed=4)
+        for T in (0, 1, 2, 9):
+            got, _ = run_gpu("7c", "f64", u0, c, arr, T, algo="mwd", params={"diamond_width": 8})
+            assert_bitwise(got, oracle_run("7c", u0, c, arr, T), "tiny %s T=%d" % (n, T))
+    u0, c, arr = inputs("25v", 5, 3, 6, seed=4)
+    got, _ = run_gpu("25v", "f64", u0, c, arr, 3, algo="mwd", params={"diamond_width": 16})
+    assert_bitwise(got, oracle_run("25v", u0, c, arr, 3), "tiny 25v")
+
+
+def test_mwd_padded_layout():
+    u0, c, arr = inputs("7v", 50, 20, 9, seed=5)
+    got, _ = run_gpu("7v", "f64", u0, c, arr, 6, params={"diamond_width": 8}, pitch=(64, 25))
+    assert_bitwise(got, oracle_run("7v", u0, c, arr, 6), "padded")
+
+
+def test_mwd_time_split_bitwise():
+    import paper_1510_04995_amd as P
+    from tests.gpu_util import torch_dev, upload
+    torch, dev = torch_dev()
+    u0, c, arr = inputs("7c", 90, 40, 16, seed=6)
+    sw = P.Sweep("7c", "f64", 90, 40, 16, list(c), "mwd", {"diamond_width": 8})
+    b0, b1 = upload(u0), upload(u0)
+    out = sw.run(b0, b1, 5)
+    other = b1 if out is b0 else b0
+    out2 = sw.run(out, other, 6)
+    whole = oracle_run("7c", u0, c, arr, 11)
+    assert_bitwise(out2.cpu().numpy(), whole, "run(5); run(6) vs run(11)")
+    sw.close()
+
+
+def test_mwd_full_size_headline_vs_naive():
+    """512^3 7-point constant, T = 64, in the benchmark's default launch
+    configuration: MWD equals the GPU naive sweep in every element, and sampled
+    points equal the oracle evaluated on their light cones."""
+    import paper_1510_04995_amd as P
+    from tests.gpu_util import torch_dev
+    from workloads import WORKLOADS
+    torch, dev = torch_dev()
+    w = WORKLOADS["7pt-const-512"]
+    u0, c, arr = inputs(w.stencil, w.nx, w.ny, w.nz, seed=0)
+    g0 = torch.from_numpy(u0).to(dev)
+    res = {}
+    for algo in ("mwd", "naive"):
+        sw = P.Sweep(w.stencil, "f64", w.nx, w.ny, w.nz, list(c), algo)
+        b0, b1 = g0.clone(), g0.clone()
+        res[algo] = sw.run(b0, b1, w.T)
+        sw.close()
+    rel, mx, nd = P.error_norms(res["mwd"], res["naive"], 1, w.nx, w.ny, w.nz)
+    assert nd == 0 and mx == 0.0
+    out = res["mwd"].cpu().numpy()
+    check_samples_against_cones(w.stencil, u0, c, arr, w.T, out,
+                                [(0, 0, 0), (511, 511, 511), (0, 255, 511), (300, 7, 129), (256, 256, 256)])
+
+
+def check_samples_against_cones(stencil, u0, c, arr, T, out, points):
+    """Oracle on the sub-box around each sample that holds its light cone."""
+    R = 1 if stencil.startswith("7") else 4
+    h = R
+    nzp, nyp, nxp = u0.shape
+    n = (nzp - 2 * h, nyp - 2 * h, nxp - 2 * h)
+    reach = R * T + R
+    for p in points:   # (z, y, x) interior indices
+        lo = [max(0, p[d] - reach) for d in range(3)]
+        hi = [min(n[d], p[d] + reach + 1) for d in range(3)]
+        sl = tuple(slice(lo[d], hi[d] + 2 * h) for d in range(3))
+        sub = np.ascontiguousarray(u0[sl])
+        sub_arr = None if arr is None else [np.ascontiguousarray(a[sl]) for a in arr]
+        r = oracle_run(stencil, sub, c, sub_arr, T)
+        q = tuple(p[d] - lo[d] + h for d in range(3))
+        full = tuple(p[d] + h for d in range(3))
+        assert r[q] == out[full], (p, r[q], out[full])

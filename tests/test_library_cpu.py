@@ -1,0 +1,120 @@
+"""Host-side checks of libgirih.so that need no GPU: the library loads, exports
+every function declared in include/girih.h, and validates plans on the host
+(plan creation touches no device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1510_04995_amd import girih as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "girih.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(girih_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("girih_plan", "girih_run", "girih_tune", "girih_plan_info", "girih_destroy", "girih_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(G.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(G.SIGNATURES)
+
+
+def test_strerror_and_version():
+    assert G.girih_strerror(0) == "ok"
+    assert "invalid" in G.girih_strerror(-1)
+    assert "gfx950" in G.girih_version()
+
+
+def grid(n=32, h=1, **kw):
+    return G.make_grid(n, n, n, h, **kw)
+
+
+def test_plan_defaults_and_info():
+    p = G.girih_plan("7c", "f64", grid(), (0.4, 0.1), "mwd")
+    params, lds, bpl = G.girih_plan_info(p)
+    assert params["diamond_width"] % 4 == 0 and params["wavefront_depth"] == 1
+    assert params["threads_y"] == params["diamond_width"] // 2
+    assert 0 < lds <= 160 * 1024
+    assert 0 < bpl < 16
+    G.girih_destroy(p)
+    p = G.girih_plan("7v", "f32", grid(), None, "naive")
+    params, lds, bpl = G.girih_plan_info(p)
+    assert bpl == pytest.approx(9 * 4)
+    G.girih_destroy(p)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(stencil="7c", g=lambda: grid(h=2), c=(0.4, 0.1)),            # halo != R
+    dict(stencil="25c", g=lambda: grid(h=1), c=(1, 0, 0, 0, 0)),       # halo != R
+    dict(stencil="7c", g=lambda: G.make_grid(0, 4, 4, 1), c=(0.4, 0.1)),  # empty
+    dict(stencil="7c", g=lambda: grid(pitch_x=10), c=(0.4, 0.1)),     # pitch too small
+    dict(stencil="7c", g=lambda: grid(), c=None),                     # missing constants
+])
+def test_plan_rejects_invalid(bad):
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan(bad["stencil"], "f64", bad["g"](), bad["c"], "mwd")
+    assert e.value.code == G.E_INVALID
+
+
+def test_plan_rejects_bad_tile_params():
+    g = grid()
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 6})   # not a multiple of 4
+    assert e.value.code == G.E_INVALID
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("25c", "f64", G.make_grid(32, 32, 32, 4), (1, 0, 0, 0, 0), "mwd", {"diamond_width": 12})
+    assert e.value.code == G.E_INVALID
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 8, "threads_x": 128, "tile_x": 4096})
+    assert e.value.code == G.E_LDS
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 40})
+    assert e.value.code == G.E_UNSUPPORTED
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"wavefront_depth": 3})
+    assert e.value.code == G.E_UNSUPPORTED
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "naive", {"threads_x": 64, "threads_y": 8})  # 512 > 256
+    assert e.value.code == G.E_INVALID
+
+
+def test_run_rejects_without_launch():
+    p = G.girih_plan("7v", "f64", grid(), None, "mwd")
+    with pytest.raises(G.GirihError) as e:
+        G.girih_run(p, 0, 0, [], 4, 0)                 # null buffers
+    assert e.value.code == G.E_INVALID
+    with pytest.raises(G.GirihError) as e:
+        G.girih_run(p, 4096, 8192, [16] * 6, 4, 0)     # 6 coefficient arrays for 7v
+    assert e.value.code == G.E_INVALID
+    with pytest.raises(G.GirihError) as e:
+        G.girih_run(p, 4096, 8192, [16] * 7, -1, 0)    # T < 0
+    assert e.value.code == G.E_INVALID
+    G.girih_destroy(p)
+
+
+def test_candidates_cover_compiled_variants():
+    p = G.girih_plan("7c", "f64", G.make_grid(512, 512, 512, 1), (0.4, 0.1), "mwd")
+    c = G.girih_candidates(p)
+    dws = {q["diamond_width"] for q in c}
+    assert {4, 8, 12, 16} <= dws
+    for q in c:
+        assert q["threads_y"] == q["diamond_width"] // 2
+        assert 8 <= q["tile_x"] <= q["threads_x"] - 2 * (q["diamond_width"] - 1)
+    G.girih_destroy(p)
+    p = G.girih_plan("25v", "f32", G.make_grid(384, 384, 384, 4), None, "mwd")
+    c = G.girih_candidates(p)
+    assert all(q["diamond_width"] % 8 == 0 for q in c) and c
+    G.girih_destroy(p)
