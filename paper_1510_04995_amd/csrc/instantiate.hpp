@@ -43,7 +43,6 @@ template <class S, typename Real>
 void add_family(std::vector<KernelEntry>& t, int st, int dt) {
     add_naive<S, Real>(t, st, dt);
     if constexpr (S::R == 1) {
-        add_mwd<S, Real, 4, 1>(t, st, dt);
         add_mwd<S, Real, 4, 2>(t, st, dt);
         add_mwd<S, Real, 4, 4>(t, st, dt);
         add_mwd<S, Real, 8, 1>(t, st, dt);
@@ -52,9 +51,9 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         add_mwd<S, Real, 12, 1>(t, st, dt);
         add_mwd<S, Real, 12, 2>(t, st, dt);
         add_mwd<S, Real, 16, 1>(t, st, dt);
-        add_mwd<S, Real, 16, 2>(t, st, dt);
         if constexpr (sizeof(Real) == 4) {
             add_mwd<S, Real, 12, 4>(t, st, dt);
+            add_mwd<S, Real, 16, 2>(t, st, dt);
             add_mwd<S, Real, 16, 4>(t, st, dt);
         }
     } else {
@@ -63,9 +62,10 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         add_mwd<S, Real, 8, 4>(t, st, dt);
         add_mwd<S, Real, 16, 1>(t, st, dt);
         add_mwd<S, Real, 16, 2>(t, st, dt);
-        add_mwd<S, Real, 24, 2>(t, st, dt);
+        add_mwd<S, Real, 24, 1>(t, st, dt);
         if constexpr (sizeof(Real) == 4) {
             add_mwd<S, Real, 16, 4>(t, st, dt);
+            add_mwd<S, Real, 24, 2>(t, st, dt);
         }
     }
 }

@@ -9,26 +9,31 @@
 //    the diamond's intermediate time levels never leave the CU;
 //  * the wavefront runs along z: at wavefront step zs, level k of the diamond
 //    updates plane zs - R*k (slope R, one plane per step: N_F = 1);
-//  * lanes run along x (VX blocks of 64 consecutive cells per lane group), so
-//    every global access is a coalesced x-row;
+//  * lanes run along x (VX blocks of 64 consecutive cells), so every global
+//    access is a coalesced x-row;
 //  * threads split the diamond along y with a fixed data subset per thread
 //    at every time level (the paper's fixed-execution-to-data wavefront):
 //    each wave owns two y-rows of the diamond, row A at half-distance d from
 //    the centre and row B at H-1-d (in blocks of R rows), so every wave
 //    updates exactly L = 2H (row, level) cells per step;
 //  * each (row, level) cell keeps its last 2R outputs along z in registers
-//    (the z-ring): z-neighbours never touch memory.  The centre plane that a
-//    level reads from its x- and y-neighbours is staged in LDS once per
-//    wavefront step; a barrier separates staging from reading, a second one
-//    protects the stage for the next step;
+//    (the z-ring): z-neighbours never touch memory;
+//  * the plane each level reads its x- and y-neighbours from is staged in
+//    LDS once per wavefront step: computed levels from their z-rings, and the
+//    cells of the previous diamond row a level needs (its entry inputs and
+//    the rows just outside it) from HBM, loaded one step ahead into
+//    registers so no HBM latency sits between two barriers;
+//  * a row's first computed level takes its z-neighbours from a "virtual"
+//    z-ring of the input time level, fed by the same one-step-ahead loads;
 //  * the x-chunk carries a shrinking halo of R*(L-1) cells per side that is
-//    recomputed redundantly (the paper keeps x whole on the CPU; on the GPU
-//    x is chunked for on-chip capacity and parallel slack).
+//    recomputed redundantly (the paper keeps x whole on the CPU; on the GPU x
+//    is chunked for on-chip capacity and parallel slack); all lanes compute
+//    every cell, values outside a level's valid range are never consumed.
 //
 // Register layout: row A may hold any level 1..L-1, row B only levels
-// KB_LO..KB_HI (the middle band every partner row lives in), both indexed by
-// the level itself, so every ring index and every LDS stage offset except the
-// row term is a compile-time constant.
+// KB_LO..KB_HI (the band every partner row lives in), both indexed by the
+// level itself, so every ring index and every LDS offset except the row term
+// is a compile-time constant.
 //
 // Buffers: diamonds of one row are independent, but redundantly computed
 // x-halos read cells that the neighbouring x-chunk of the same diamond may
@@ -38,9 +43,15 @@
 // is the last two time levels computed there, stored by parity t%2: a diamond
 // stores a value iff it does not itself compute the value two levels later,
 // and copies the input levels at rows where it computes fewer than two.
+//
+// Dirichlet halo: if the halo of the input is all zero (a flag computed on
+// the device before the sweep) halo rows of the stage are zero-filled once
+// and halo lanes and planes are set to zero; otherwise halo values are loaded
+// where they are needed (slower, same result).
 #pragma once
-#include "stencils.hpp"
 #include <type_traits>
+
+#include "stencils.hpp"
 
 namespace girih {
 
@@ -55,8 +66,8 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // Opaque copies: the compiler must assume the value changed, so expressions
 // derived from it are recomputed where they are used instead of being hoisted
-// out of the wavefront loop (which would keep dozens of per-slot scalars and
-// lane masks alive across the whole loop and spill them).
+// out of the wavefront loop (which would keep dozens of per-slot scalars
+// alive across the loop and spill them).
 __device__ __forceinline__ int opaque_s(int v) {
     v = __builtin_amdgcn_readfirstlane(v);
     asm volatile("" : "+s"(v));
@@ -67,8 +78,6 @@ __device__ __forceinline__ int64_t opaque_s(int64_t v) {
     int hi = opaque_s((int)(uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
-template <typename T>
-__device__ __forceinline__ T opaque_v(T v) { asm volatile("" : "+v"(v)); return v; }
 
 template <typename Real>
 struct MwdArgs {
@@ -76,6 +85,7 @@ struct MwdArgs {
     const Real* in[2];   // input pair, indexed by time parity
     Real* out[2];        // output pair, indexed by time parity
     CoefArgs<Real> coef;
+    const int* zero_halo;  // device flag: 1 if every halo cell of the input is zero
     int64_t T;           // total number of time steps of the run
     int64_t t_c;         // row centre time: row r has t_c = r*H
     int64_t c_first;     // y centre of the diamond with blockIdx.y == 0
@@ -90,16 +100,17 @@ struct DiamondShape {
     static constexpr int L = 2 * H;
     // half-width of level k (level k is time step t_c - H + k)
     static constexpr int w(int k) { return k < H ? R * k : DW / 2 - R * (k - H); }
-    static constexpr int row_lo(int k) { return DW / 2 - w(k); }
-    static constexpr int stage_base(int k) {
+    // stage level k (0..L-2) holds the rows level k+1 reads: Y_{k+1} +- R
+    static constexpr int sl_lo(int k) { return DW / 2 - w(k + 1) - R; }
+    static constexpr int nrows(int k) { return 2 * w(k + 1) + 2 * R; }
+    static constexpr int sbase(int k) {
         int b = 0;
-        for (int q = 0; q < k; ++q) b += 2 * w(q);
+        for (int q = 0; q < k; ++q) b += nrows(q);
         return b;
     }
-    // LDS row of (level k, local row j) is stage_row0(k) + j
-    static constexpr int stage_row0(int k) { return stage_base(k) - row_lo(k); }
-    // levels 0..L-2 are staged (level L-1 feeds no later level of the diamond)
-    static constexpr int STAGE_ROWS = stage_base(L - 1) > 0 ? stage_base(L - 1) : 1;
+    // LDS row of (stage level k, local row j) is srow0(k) + j
+    static constexpr int srow0(int k) { return sbase(k) - sl_lo(k); }
+    static constexpr int STAGE_ROWS = sbase(L - 1);
     // the band of levels a partner (row B) can hold
     static constexpr int BMIN = H / 2;
     static constexpr int KB_LO = BMIN + 1;
@@ -122,8 +133,8 @@ __host__ __device__ inline int partner_of(int d) {
     return b2 != b ? b2 * Sh::R + e : b * Sh::R + (e ^ 1);
 }
 
-// Level range [kf, kl] computed at local row j of a diamond whose local row 0
-// is global row y0 (empty: kf > kl).
+// Level range [kf, kl] computed at local row j whose global row is y
+// (empty: kf > kl).
 template <class Sh>
 __host__ __device__ inline void row_levels(int j, int64_t y, int64_t ny, int64_t t_c, int64_t T,
                                            int& kf, int& kl) {
@@ -147,132 +158,31 @@ struct MwdKernel {
     static constexpr int NWAVES = DW / 2;
     static constexpr int NT = 64 * NWAVES;
     static constexpr int XL = 64 * VX;          // x cells held per row
+    static constexpr int XLP = XL + 2 * R;      // LDS row stride (R guard cells per side)
     static constexpr int HX = R * (L - 1);      // redundant x halo per side
     static constexpr int XOWN_MAX = XL - 2 * HX;
-    static constexpr int LDS_BYTES = Sh::STAGE_ROWS * XL * (int)sizeof(Real);
+    static constexpr int LDS_BYTES = Sh::STAGE_ROWS * XLP * (int)sizeof(Real);
     static constexpr int RING = 2 * R;
-    static constexpr int RING_VALUES = (Sh::NA + Sh::NB) * RING * VX;
 };
 
-// Per-row state of one wave: the row, its level range, and for r = 1..R bit
-// masks over levels k telling whether level k finds its y-neighbour row j-r
-// (ym) or j+r (yp) computed at level k-1 inside the diamond (then it reads the
-// LDS stage, else the input buffer).
-template <int R>
-struct RowState {
-    int j;
-    int64_t y;
-    int kf, kl;
-    uint32_t ym[R], yp[R];
+// One-step-ahead registers of an owned row: the cells of earlier diamond rows
+// it needs.
+template <typename Real, int R, int VX>
+struct RowRegs {
+    Real vring[2 * R][VX];   // z-ring of the input level kf-1 (virtual level)
+    Real vnext[VX];          // input level, plane produced at the coming step
+    Real pre2[VX];           // level kf-2 centre plane for the coming step's stage
+    Real preo[VX];           // out-of-span neighbour row for the coming step's stage
 };
-
-template <class Sh>
-__device__ __forceinline__ void init_row(RowState<Sh::R>& rs, int j, int64_t ybase, int64_t ny,
-                                         int64_t t_c, int64_t T) {
-    rs.j = j;
-    rs.y = ybase + j;
-    row_levels<Sh>(j, rs.y, ny, t_c, T, rs.kf, rs.kl);
-#pragma unroll
-    for (int r = 1; r <= Sh::R; ++r) {
-        int f, l;
-        row_levels<Sh>(j - r, rs.y - r, ny, t_c, T, f, l);
-        rs.ym[r - 1] = f <= l ? (((2u << l) - 1u) & ~((1u << f) - 1u)) << 1 : 0u;
-        row_levels<Sh>(j + r, rs.y + r, ny, t_c, T, f, l);
-        rs.yp[r - 1] = f <= l ? (((2u << l) - 1u) & ~((1u << f) - 1u)) << 1 : 0u;
-    }
-}
-
-// One (row, level K) cell update for all VX x-blocks of the lane.
-//   prev: z-ring of (row, K-1) (valid when K > kf); nvprev: its output this step
-//   nv:   output of (row, K) this step (plane zs - R*K)
-template <class S, typename Real, int DW, int VX, int K>
-__device__ __forceinline__ void update_cell(const MwdArgs<Real>& a, Real* __restrict__ stage,
-                                            const RowState<S::R>& rs, const Real (&prev)[2 * S::R][VX],
-                                            const Real (&nvprev)[VX], Real (&nv)[VX], int ph, int64_t zs,
-                                            int lane, int64_t x0, int ow) {
-    using KK = MwdKernel<S, Real, DW, VX>;
-    using Sh = typename KK::Sh;
-    constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = 2 * R, XL = KK::XL;
-    const GridDesc& g = a.g;
-#pragma unroll
-    for (int v = 0; v < VX; ++v) nv[v] = Real(0);
-    const int kf = opaque_s(rs.kf), kl = opaque_s(rs.kl);
-    if (K < kf || K > kl) return;
-    const int64_t q = opaque_s(zs) - (int64_t)R * K;
-    if (q < -R || q >= g.nz + R) return;
-    const int64_t s_in = a.t_c - H + K;                 // time level of the inputs
-    const Real* __restrict__ src = a.in[s_in & 1];
-    const bool from_ring = K > kf;
-    const bool q_in = q >= 0 && q < g.nz;
-    const bool store_out = K >= kl - 1;
-    const bool copy_in = kf == kl;
-    const int64_t rowoff = ((q + g.h) * g.pitch_y + (opaque_s(rs.y) + g.h)) * g.pitch_x + g.h;
-    lane = opaque_v(lane);
-    ow = opaque_s(ow);
-    x0 = opaque_s(x0);
-    Real* out_new = a.out[(s_in + 1) & 1] + rowoff;
-    Real* out_old = a.out[s_in & 1] + rowoff;
-    const Real* srow = src + rowoff;
-    const int64_t plane = g.plane();
-    const int64_t px = g.pitch_x;
-    // LDS rows of level K-1: own row, and rows j -/+ r
-    const Real* st = stage + (Sh::stage_row0(K - 1 < 0 ? 0 : K - 1) + opaque_s(rs.j)) * XL;
-#pragma unroll
-    for (int v = 0; v < VX; ++v) {
-        const int col = lane + 64 * v;
-        const int64_t x = x0 + col;
-        const bool x_in = x >= 0 && x < g.nx;
-        const bool comp = q_in && x_in && col >= R * K && col < ow + R * (2 * L - 2 - K);
-        if (comp) {
-            Nbhd<Real, R> n;
-            const Real* sp = srow + x;
-            if (from_ring) {
-                n.c = prev[(ph + R) % RING][v];
-#pragma unroll
-                for (int r = 1; r <= R; ++r) {
-                    n.zm[r - 1] = prev[(ph + R - r) % RING][v];
-                    n.zp[r - 1] = r == R ? nvprev[v] : prev[(ph + R + r) % RING][v];
-                    n.xp[r - 1] = st[col + r];
-                    n.xm[r - 1] = st[col - r];
-                }
-            } else {
-                n.c = sp[0];
-#pragma unroll
-                for (int r = 1; r <= R; ++r) {
-                    n.zm[r - 1] = sp[-r * plane];
-                    n.zp[r - 1] = sp[r * plane];
-                    n.xp[r - 1] = sp[r];
-                    n.xm[r - 1] = sp[-r];
-                }
-            }
-#pragma unroll
-            for (int r = 1; r <= R; ++r) {
-                n.yp[r - 1] = (rs.yp[r - 1] >> K) & 1u ? st[col + r * XL] : sp[r * px];
-                n.ym[r - 1] = (rs.ym[r - 1] >> K) & 1u ? st[col - r * XL] : sp[-r * px];
-            }
-            Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
-#pragma unroll
-            for (int m = 0; m < S::NCOEF; ++m) cf[m] = a.coef.arr[m][rowoff + x];
-            const Real u = S::apply(n, a.coef.k, cf);
-            nv[v] = u;
-            if (col >= KK::HX && col < KK::HX + ow) {
-                if (store_out) out_new[x] = u;
-                if (copy_in) out_old[x] = n.c;
-            }
-        } else if (x >= -R && x < g.nx + R && (!q_in || !x_in)) {
-            nv[v] = srow[x];                       // fixed Dirichlet halo (same in every buffer)
-        }
-    }
-}
 
 template <class S, typename Real, int DW, int VX>
 __global__ void __launch_bounds__(64 * (DW / 2))
 mwd_row_kernel(MwdArgs<Real> a) {
     using KK = MwdKernel<S, Real, DW, VX>;
     using Sh = typename KK::Sh;
-    constexpr int R = S::R, L = Sh::L, RING = KK::RING, XL = KK::XL;
+    constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
     constexpr int NA = Sh::NA, NB = Sh::NB, KB_LO = Sh::KB_LO;
-    __shared__ Real stage[Sh::STAGE_ROWS * XL];
+    __shared__ Real stage[Sh::STAGE_ROWS * XLP];
 
     const GridDesc& g = a.g;
     const int lane = threadIdx.x & 63;
@@ -281,8 +191,22 @@ mwd_row_kernel(MwdArgs<Real> a) {
     const int64_t ybase = c - DW / 2;                           // global y of local row 0
     const int64_t x_own_lo = (int64_t)blockIdx.x * a.x_own;
     const int64_t x_own_hi = x_own_lo + a.x_own < g.nx ? x_own_lo + a.x_own : g.nx;
-    const int ow = (int)(x_own_hi - x_own_lo);
     const int64_t x0 = x_own_lo - KK::HX;                       // x of column 0
+    const int zero_halo = __builtin_amdgcn_readfirstlane(*a.zero_halo);
+    const bool edge_x = x0 < 0 || x0 + KK::XL > g.nx;          // chunk touches the x halo
+    const bool edge_y = ybase - R < 0 || ybase + DW + R > g.ny; // diamond touches the y halo
+
+    // per-lane constants: clamped element offset within a row, ownership, x-halo
+    int xo[VX];
+    bool own[VX], xh[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const int64_t x = x0 + lane + 64 * v;
+        const int64_t xc = x < -R ? -R : (x >= g.nx + R ? g.nx + R - 1 : x);
+        xo[v] = (int)(xc + g.h);
+        own[v] = x >= x_own_lo && x < x_own_hi;
+        xh[v] = (x >= -R && x < 0) || (x >= g.nx && x < g.nx + R);
+    }
 
     // ---- this wave's two rows ------------------------------------------------
     const int per_side = DW / 4;
@@ -296,12 +220,68 @@ mwd_row_kernel(MwdArgs<Real> a) {
             --p;
         }
     }
-    RowState<R> A, B;
-    init_row<Sh>(A, side == 0 ? DW / 2 + dA : DW / 2 - 1 - dA, ybase, g.ny, a.t_c, a.T);
-    init_row<Sh>(B, side == 0 ? DW / 2 + dB : DW / 2 - 1 - dB, ybase, g.ny, a.t_c, a.T);
+    const int jA = side == 0 ? DW / 2 + dA : DW / 2 - 1 - dA;
+    const int jB = side == 0 ? DW / 2 + dB : DW / 2 - 1 - dB;
+    int kfA, klA, kfB, klB;
+    row_levels<Sh>(jA, ybase + jA, g.ny, a.t_c, a.T, kfA, klA);
+    row_levels<Sh>(jB, ybase + jB, g.ny, a.t_c, a.T, kfB, klB);
+    // The outermost block of rows reads, at level H, the rows up to R beyond
+    // the diamond at level H-1 (time t_c).  The owner of an outermost row j
+    // stages the row R further out (j+R on the right, j-R on the left); it does
+    // so whether or not its own row is inside the grid.
+    auto out_row = [&](int d, int j) -> int {
+        if (d / R != H - 1 || a.t_c >= a.T) return -1000;
+        const int jo = side == 0 ? j + R : j - R;
+        const int64_t yo = ybase + jo;
+        return yo >= -R && yo < g.ny + R ? jo : -1000;
+    };
+    const int joA = out_row(dA, jA);
+    const int joB = out_row(dB, jB);
+
+    const int64_t plane = g.plane();
+    // element offset of (plane q, global row y); q clamped into the haloed box
+    auto rowoff = [&](int64_t q, int64_t y) -> int64_t {
+        q = q < -R ? -R : (q >= g.nz + R ? g.nz + R - 1 : q);
+        return (q + g.h) * plane + (y + g.h) * g.pitch_x;
+    };
+    auto srow = [&](int k, int j) -> Real* { return stage + (Sh::srow0(k) + j) * XLP + R; };
+    auto load_row = [&](const Real* base, int64_t off, Real (&dst)[VX]) {
+        const Real* rp = base + off;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) dst[v] = rp[xo[v]];
+    };
+    auto put_row = [&](Real* sp, const Real (&src)[VX]) {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) sp[lane + 64 * v] = src[v];
+    };
+
+    // Halo rows of the stage (rows outside the grid, inside it +-R): with a zero
+    // halo they are written once here and never touched again.
+    if (edge_y && zero_halo) {
+        for (int k = 0; k < L - 1; ++k) {
+            for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
+                const int64_t y = ybase + j;
+                if ((y >= -R && y < 0) || (y >= g.ny && y < g.ny + R)) {
+                    Real* sp = srow(k, j) - R;
+                    for (int col = threadIdx.x; col < XLP; col += KK::NT) sp[col] = Real(0);
+                }
+            }
+        }
+    }
 
     Real ringA[NA][RING][VX];
     Real ringB[NB][RING][VX];
+    RowRegs<Real, R, VX> RA, RB;
+    auto zero_regs = [&](RowRegs<Real, R, VX>& rr) {
+#pragma unroll
+        for (int m = 0; m < RING; ++m)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) rr.vring[m][v] = Real(0);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) rr.vnext[v] = rr.pre2[v] = rr.preo[v] = Real(0);
+    };
+    zero_regs(RA);
+    zero_regs(RB);
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
@@ -315,6 +295,23 @@ mwd_row_kernel(MwdArgs<Real> a) {
 #pragma unroll
             for (int v = 0; v < VX; ++v) ringB[i][m][v] = Real(0);
 
+    // One-step-ahead loads of a row for step `zs`: the input level kf-1 at the
+    // plane it "produces" at that step, and the stage rows of that step.
+    auto prefetch = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, int jo, int64_t zs) {
+        if (jo > -1000) load_row(a.in[a.t_c & 1], rowoff(zs - (int64_t)R * H, ybase + jo), rr.preo);
+        if (kf > kl) return;
+        const int64_t y = ybase + j;
+        const int64_t s_in = a.t_c - H + kf;     // time level of the entry inputs (>= 0)
+        load_row(a.in[s_in & 1], rowoff(zs - (int64_t)R * (kf - 1), y), rr.vnext);
+        if (kf >= 2 && s_in >= 1)
+            load_row(a.in[(s_in - 1) & 1], rowoff(zs - (int64_t)R * (kf - 1), y), rr.pre2);
+    };
+
+    // prologue: loads for step 0
+    prefetch(RA, jA, kfA, klA, joA, 0);
+    prefetch(RB, jB, kfB, klB, joB, 0);
+    __syncthreads();
+
     const int64_t nzs = g.nz + (int64_t)R * (L - 1);   // wavefront steps
 
     for (int64_t zb = 0; zb < nzs; zb += RING) {
@@ -322,81 +319,147 @@ mwd_row_kernel(MwdArgs<Real> a) {
             constexpr int ph = decltype(phc)::value;
             const int64_t zs = zb + ph;
             const bool live = zs < nzs;          // uniform across the workgroup
-            // ---- A: stage the centre planes the next levels read this step ----
+            Real vcurA[VX], vcurB[VX];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) { vcurA[v] = RA.vnext[v]; vcurB[v] = RB.vnext[v]; }
+            // ---- A: stage every plane the levels read this step ------------------
             if (live) {
+                const int kfa = opaque_s(kfA), kla = opaque_s(klA), kfb = opaque_s(kfB), klb = opaque_s(klB);
+                const int ja = opaque_s(jA), jb = opaque_s(jB);
                 static_for<0, NA>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     constexpr int k = 1 + i;
                     if constexpr (k <= L - 2) {
-                        const int64_t q = zs - (int64_t)R * (k + 1);
-                        if (k >= A.kf && k <= A.kl && q >= 0 && q < g.nz) {
-                            Real* st = stage + (Sh::stage_row0(k) + A.j) * XL + lane;
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) st[64 * v] = ringA[i][(ph + RING - R) % RING][v];
-                        }
+                        if (k >= kfa && k <= kla) put_row(srow(k, ja), ringA[i][(ph + RING - R) % RING]);
                     }
                 });
                 static_for<0, NB>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     constexpr int k = KB_LO + i;
                     if constexpr (k <= L - 2) {
-                        const int64_t q = zs - (int64_t)R * (k + 1);
-                        if (k >= B.kf && k <= B.kl && q >= 0 && q < g.nz) {
-                            Real* st = stage + (Sh::stage_row0(k) + B.j) * XL + lane;
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) st[64 * v] = ringB[i][(ph + RING - R) % RING][v];
-                        }
+                        if (k >= kfb && k <= klb) put_row(srow(k, jb), ringB[i][(ph + RING - R) % RING]);
                     }
                 });
+                auto stage_row = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, int jo) {
+                    if (jo > -1000) put_row(srow(H - 1, jo), rr.preo);
+                    if (kf > kl) return;
+                    put_row(srow(kf - 1, j), rr.vring[(ph + RING - R) % RING]);
+                    if (kf >= 2) put_row(srow(kf - 2, j), rr.pre2);
+                };
+                stage_row(RA, ja, kfa, kla, opaque_s(joA));
+                stage_row(RB, jb, kfb, klb, opaque_s(joB));
+                // halo rows with a non-zero halo: load them (latency exposed; edge diamonds only)
+                if (edge_y && !zero_halo) {
+                    for (int k = wave; k < L - 1; k += KK::NWAVES) {
+                        for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
+                            const int64_t y = ybase + j;
+                            if ((y >= -R && y < 0) || (y >= g.ny && y < g.ny + R)) {
+                                Real tmp[VX];
+                                load_row(a.in[0], rowoff(zs - (int64_t)R * (k + 1), y), tmp);
+                                put_row(srow(k, j), tmp);
+                            }
+                        }
+                    }
+                }
+                // loads for the next step
+                prefetch(RA, ja, kfa, kla, opaque_s(joA), zs + 1);
+                prefetch(RB, jb, kfb, klb, opaque_s(joB), zs + 1);
             }
             __syncthreads();
             // ---- B: update every owned (row, level) cell of this step ----------
             if (live) {
-                Real nvprev[VX], nv[VX];
+                auto run_row = [&](auto& ring, auto kbase_c, RowRegs<Real, R, VX>& rr, const Real (&vcur)[VX],
+                                   int jr, int kf, int kl) {
+                    constexpr int KBASE = decltype(kbase_c)::value;
+                    constexpr int NS = sizeof(ring) / sizeof(ring[0]);
+                    const int64_t y = ybase + jr;
+                    Real prev[VX];   // output of level k-1 at this step (z + R neighbour)
 #pragma unroll
-                for (int v = 0; v < VX; ++v) nvprev[v] = Real(0);
-                static_for<0, NA>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    update_cell<S, Real, DW, VX, 1 + i>(a, stage, A, ringA[i > 0 ? i - 1 : 0], nvprev, nv,
-                                                        ph, zs, lane, x0, ow);
-                    if constexpr (i > 0) {
+                    for (int v = 0; v < VX; ++v) prev[v] = vcur[v];
+                    static_for<0, NS>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        constexpr int K = KBASE + i;
+                        Real nv[VX];
 #pragma unroll
-                        for (int v = 0; v < VX; ++v) ringA[i - 1][ph][v] = nvprev[v];
-                    }
+                        for (int v = 0; v < VX; ++v) nv[v] = Real(0);
+                        if (K >= kf && K <= kl) {
+                            const int64_t q = opaque_s(zs) - (int64_t)R * K;
+                            const bool entry = K == kf;
+                            // z-window of level K-1: ring of slot i-1, or the input ring
+                            Real zw[RING][VX];
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) nvprev[v] = nv[v];
-                });
+                            for (int m = 0; m < RING; ++m)
 #pragma unroll
-                for (int v = 0; v < VX; ++v) ringA[NA - 1][ph][v] = nvprev[v];
+                                for (int v = 0; v < VX; ++v) {
+                                    if constexpr (i == 0) zw[m][v] = rr.vring[m][v];
+                                    else zw[m][v] = entry ? rr.vring[m][v] : ring[i - 1][m][v];
+                                }
+                            if (q >= 0 && q < g.nz) {
+                                const int64_t s_in = a.t_c - H + K;          // input time level
+                                const int64_t ro = rowoff(q, y);
+                                const Real* st = srow(K - 1, jr);
 #pragma unroll
-                for (int v = 0; v < VX; ++v) nvprev[v] = Real(0);
-                static_for<0, NB>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    update_cell<S, Real, DW, VX, KB_LO + i>(a, stage, B, ringB[i > 0 ? i - 1 : 0], nvprev, nv,
-                                                            ph, zs, lane, x0, ow);
-                    if constexpr (i > 0) {
+                                for (int v = 0; v < VX; ++v) {
+                                    const int col = lane + 64 * v;
+                                    Nbhd<Real, R> n;
+                                    n.c = zw[(ph + R) % RING][v];
 #pragma unroll
-                        for (int v = 0; v < VX; ++v) ringB[i - 1][ph][v] = nvprev[v];
-                    }
+                                    for (int r = 1; r <= R; ++r) {
+                                        n.zm[r - 1] = zw[(ph + R - r) % RING][v];
+                                        n.zp[r - 1] = r == R ? prev[v] : zw[(ph + R + r) % RING][v];
+                                        n.xp[r - 1] = st[col + r];
+                                        n.xm[r - 1] = st[col - r];
+                                        n.yp[r - 1] = st[col + r * XLP];
+                                        n.ym[r - 1] = st[col - r * XLP];
+                                    }
+                                    Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) nvprev[v] = nv[v];
-                });
+                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = a.coef.arr[m][ro + xo[v]];
+                                    Real u = S::apply(n, a.coef.k, cf);
+                                    if (edge_x && xh[v]) u = zero_halo ? Real(0) : a.in[0][ro + xo[v]];
+                                    nv[v] = u;
+                                    if (own[v]) {
+                                        if (K >= kl - 1) a.out[(s_in + 1) & 1][ro + xo[v]] = u;
+                                        if (kf == kl) a.out[s_in & 1][ro + xo[v]] = n.c;
+                                    }
+                                }
+                            } else if (!zero_halo && q >= -R && q < g.nz + R) {
+                                load_row(a.in[0], rowoff(q, y), nv);   // fixed halo plane
+                            }
+                        }
+                        if constexpr (i > 0) {
 #pragma unroll
-                for (int v = 0; v < VX; ++v) ringB[NB - 1][ph][v] = nvprev[v];
+                            for (int v = 0; v < VX; ++v) ring[i - 1][ph][v] = prev[v];
+                        }
+                        // prev stays the input level's output until the row's first level
+                        if (K >= kf && K <= kl) {
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) prev[v] = nv[v];
+                        }
+                    });
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) ring[NS - 1][ph][v] = prev[v];
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) rr.vring[ph][v] = vcur[v];
+                };
+                run_row(ringA, std::integral_constant<int, 1>{}, RA, vcurA, opaque_s(jA), opaque_s(kfA),
+                        opaque_s(klA));
+                run_row(ringB, std::integral_constant<int, KB_LO>{}, RB, vcurB, opaque_s(jB), opaque_s(kfB),
+                        opaque_s(klB));
                 // rows of this diamond with no level in this row: carry both levels
                 if (zs < g.nz) {
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        const RowState<R>& rs = t == 0 ? A : B;
-                        if (rs.kf > rs.kl && rs.y >= 0 && rs.y < g.ny) {
-                            const int64_t rowoff = ((zs + g.h) * g.pitch_y + (rs.y + g.h)) * g.pitch_x + g.h;
+                        const int jr = t == 0 ? jA : jB;
+                        const int kf = t == 0 ? kfA : kfB, kl = t == 0 ? klA : klB;
+                        const int64_t y = ybase + jr;
+                        if (kf > kl && y >= 0 && y < g.ny) {
+                            const int64_t ro = rowoff(zs, y);
 #pragma unroll
                             for (int v = 0; v < VX; ++v) {
-                                const int col = lane + 64 * v;
-                                if (col >= KK::HX && col < KK::HX + ow) {
-                                    const int64_t x = x0 + col;
-                                    a.out[0][rowoff + x] = a.in[0][rowoff + x];
-                                    a.out[1][rowoff + x] = a.in[1][rowoff + x];
+                                if (own[v]) {
+                                    a.out[0][ro + xo[v]] = a.in[0][ro + xo[v]];
+                                    a.out[1][ro + xo[v]] = a.in[1][ro + xo[v]];
                                 }
                             }
                         }

@@ -40,6 +40,8 @@ const std::vector<KernelEntry>& kernel_table();
 // utility kernels (util.hip)
 hipError_t launch_copy_halo(const void* src, void* dst, int elem_bytes, int64_t nx, int64_t ny, int64_t nz,
                             int64_t h, int64_t pitch_x, int64_t pitch_y, hipStream_t s);
+hipError_t launch_zero_halo_flag(const void* src, int* flag, int elem_bytes, int64_t nx, int64_t ny, int64_t nz,
+                                 int64_t h, int64_t pitch_x, int64_t pitch_y, hipStream_t s);
 hipError_t error_norms(const void* a, int dta, const void* b, int dtb, int64_t nx, int64_t ny, int64_t nz,
                        int64_t h, int64_t pitch_x, int64_t pitch_y, hipStream_t s, double out[4]);
 

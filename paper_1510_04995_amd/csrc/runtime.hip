@@ -77,6 +77,7 @@ struct girih_plan_s {
     int R = 1;
     int64_t x_own = 0, n_xchunks = 0;
     void* scratch[2] = {nullptr, nullptr};
+    int* halo_flag = nullptr;            // device int: input halo is all zero
     size_t scratch_bytes = 0;
     int scratch_device = -1;
     Tuning tuning;
@@ -224,6 +225,12 @@ int ensure_scratch(girih_plan_s* p) {
             return GIRIH_E_NOMEM;
         }
     }
+    if (p->halo_flag) (void)hipFree(p->halo_flag);
+    p->halo_flag = nullptr;
+    if (hipMalloc(&p->halo_flag, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GIRIH_E_NOMEM;
+    }
     p->scratch_bytes = need;
     p->scratch_device = dev;
     return GIRIH_OK;
@@ -239,6 +246,7 @@ int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, i
     // every array carries buf0's fixed halo
     HIPCHK(launch_copy_halo(buf0, p->scratch[0], eb, nx, ny, nz, h, px, py, s));
     HIPCHK(launch_copy_halo(buf0, p->scratch[1], eb, nx, ny, nz, h, px, py, s));
+    HIPCHK(launch_zero_halo_flag(buf0, p->halo_flag, eb, nx, ny, nz, h, px, py, s));
     const int dw = p->kern->dw;
     const int64_t H = dw / (2 * p->R);
     const int64_t n_rows = (T - 1) / H + 2;
@@ -254,6 +262,7 @@ int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, i
     fill_coefs<Real>(p, coefs, a.coef);
     a.T = T;
     a.x_own = (int32_t)p->x_own;
+    a.zero_halo = p->halo_flag;
     const dim3 block(p->kern->nthreads);
     for (int64_t r = 0; r < n_rows; ++r) {
         Real** in = in_user ? user : scr;
@@ -479,6 +488,7 @@ int girih_plan_set_params(girih_plan_t p, const girih_params* params) {
     if (!p) return GIRIH_E_INVALID;
     girih_plan_s tmp = *p;
     tmp.scratch[0] = tmp.scratch[1] = nullptr;   // not owned by the copy
+    tmp.halo_flag = nullptr;
     int rc = resolve(&tmp, params);
     if (rc) return rc;
     p->params = tmp.params;
@@ -655,6 +665,7 @@ void girih_destroy(girih_plan_t p) {
     if (!p) return;
     for (int i = 0; i < 2; ++i)
         if (p->scratch[i]) (void)hipFree(p->scratch[i]);
+    if (p->halo_flag) (void)hipFree(p->halo_flag);
     delete p;
 }
 

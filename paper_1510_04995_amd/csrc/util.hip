@@ -39,6 +39,41 @@ hipError_t launch_copy_halo(const void* src, void* dst, int elem_bytes, int64_t 
     return hipGetLastError();
 }
 
+// flag <- 1, then flag <- 0 if any halo cell of src has a non-zero bit
+// pattern (so -0.0 counts as non-zero).
+__global__ void set_flag_kernel(int* flag, int v) { *flag = v; }
+
+template <typename T, typename U>
+__global__ void __launch_bounds__(64)
+zero_halo_kernel(const T* __restrict__ src, int* flag, int64_t nx, int64_t ny, int64_t nz, int64_t h,
+                 int64_t pitch_x, int64_t pitch_y) {
+    const int64_t jj = blockIdx.x, kk = blockIdx.y;
+    const int64_t base = (kk * pitch_y + jj) * pitch_x;
+    const U* s = reinterpret_cast<const U*>(src);
+    const bool whole = kk < h || kk >= nz + h || jj < h || jj >= ny + h;
+    bool nz_found = false;
+    if (whole) {
+        for (int64_t i = threadIdx.x; i < nx + 2 * h; i += blockDim.x) nz_found |= s[base + i] != 0;
+    } else if (threadIdx.x < 2 * h) {
+        const int64_t i = threadIdx.x < h ? threadIdx.x : nx + threadIdx.x;
+        nz_found = s[base + i] != 0;
+    }
+    if (nz_found) *flag = 0;
+}
+
+hipError_t launch_zero_halo_flag(const void* src, int* flag, int elem_bytes, int64_t nx, int64_t ny, int64_t nz,
+                                 int64_t h, int64_t pitch_x, int64_t pitch_y, hipStream_t s) {
+    hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, flag, 1);
+    const dim3 grid((unsigned)(ny + 2 * h), (unsigned)(nz + 2 * h));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL((zero_halo_kernel<double, unsigned long long>), grid, dim3(64), 0, s, (const double*)src,
+                           flag, nx, ny, nz, h, pitch_x, pitch_y);
+    else
+        hipLaunchKernelGGL((zero_halo_kernel<float, unsigned int>), grid, dim3(64), 0, s, (const float*)src, flag,
+                           nx, ny, nz, h, pitch_x, pitch_y);
+    return hipGetLastError();
+}
+
 // Partial sums per block: [sum (a-b)^2, sum b^2, max |a-b|, #bitwise-different]
 template <typename TA, typename TB>
 __global__ void __launch_bounds__(256)

@@ -50,12 +50,13 @@ def test_naive_block_shapes():
 
 # (stencil, dtype, Dw, cells per lane, tile_x or 0, grid (nx, ny, nz), list of T)
 MWD_CASES = [
-    ("7c", "f64", 4, 1, 0, (61, 23, 17), [1, 2, 3, 5, 8]),
+    ("7c", "f64", 4, 2, 0, (61, 23, 17), [1, 2, 3, 5, 8]),
     ("7c", "f64", 8, 2, 0, (150, 45, 19), [1, 4, 5, 9, 13]),
     ("7c", "f64", 8, 2, 40, (150, 45, 19), [7]),
     ("7c", "f64", 12, 2, 0, (131, 50, 12), [6, 7, 16]),
     ("7c", "f64", 16, 1, 0, (70, 70, 9), [3, 8, 17]),
-    ("7c", "f64", 16, 2, 0, (200, 40, 11), [9, 16]),
+    ("7c", "f64", 12, 1, 0, (200, 40, 11), [9, 16]),
+    ("7c", "f32", 16, 2, 0, (200, 40, 11), [9, 16]),
     ("7c", "f32", 8, 4, 0, (300, 33, 15), [5, 12]),
     ("7c", "f32", 16, 4, 0, (260, 37, 9), [10]),
     ("7v", "f64", 8, 2, 0, (129, 30, 14), [3, 7]),
@@ -63,7 +64,8 @@ MWD_CASES = [
     ("25c", "f64", 8, 2, 0, (140, 30, 20), [1, 2, 3]),
     ("25c", "f64", 16, 2, 0, (150, 50, 22), [2, 3, 5]),
     ("25c", "f32", 16, 4, 0, (260, 45, 17), [4]),
-    ("25c", "f64", 24, 2, 0, (100, 60, 21), [3, 7]),
+    ("25c", "f64", 24, 1, 0, (100, 60, 21), [3, 7]),
+    ("25c", "f32", 24, 2, 0, (100, 60, 21), [3, 7]),
     ("25v", "f64", 16, 2, 0, (130, 40, 19), [2, 5]),
     ("25v", "f32", 8, 4, 0, (250, 26, 18), [3]),
 ]
@@ -158,3 +160,21 @@ def check_samples_against_cones(stencil, u0, c, arr, T, out, points):
         q = tuple(p[d] - lo[d] + h for d in range(3))
         full = tuple(p[d] + h for d in range(3))
         assert r[q] == out[full], (p, r[q], out[full])
+
+
+@pytest.mark.parametrize("stencil,dw,vx,n,T", [("7c", 8, 2, (140, 37, 13), 9), ("7v", 12, 2, (131, 29, 11), 7),
+                                               ("25c", 16, 2, (120, 45, 19), 5), ("25v", 8, 2, (90, 21, 17), 3)])
+def test_mwd_nonzero_halo(stencil, dw, vx, n, T):
+    """Arbitrary fixed Dirichlet values (and a -0.0) in the halo take the general path."""
+    u0, c, arr = inputs(stencil, *n, seed=8)
+    h = 1 if stencil.startswith("7") else 4
+    rng = np.random.default_rng(3)
+    halo = np.ones(u0.shape, dtype=bool)
+    halo[h:-h, h:-h, h:-h] = False
+    u0 = u0.copy()
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    u0[0, 0, 0] = -0.0
+    got, _ = run_gpu(stencil, "f64", u0, c, arr, T, algo="mwd", params={"diamond_width": dw, "threads_x": 64 * vx})
+    assert_bitwise(got, oracle_run(stencil, u0, c, arr, T), "nonzero halo %s" % stencil)
+    got32, _ = run_gpu(stencil, "f32", u0, c, arr, T, algo="mwd", params={"diamond_width": dw, "threads_x": 64 * vx})
+    assert_bitwise(got32, oracle_run(stencil, u0, c, arr, T, "f32"), "nonzero halo f32 %s" % stencil)
