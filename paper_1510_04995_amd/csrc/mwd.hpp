@@ -171,8 +171,20 @@ template <typename Real, int R, int VX>
 struct RowRegs {
     Real vring[2 * R][VX];   // z-ring of the input level kf-1 (virtual level)
     Real vnext[VX];          // input level, plane produced at the coming step
-    Real pre2[VX];           // level kf-2 centre plane for the coming step's stage
+    Real pre1[VX];           // stage duty kv of a row that computes nothing here
+    Real pre2[VX];           // stage duty kv-1
     Real preo[VX];           // out-of-span neighbour row for the coming step's stage
+};
+
+// Stage duties of one owned row.  Level k of the stage holds the time level
+// t_c-H+k+1 that level k+1 reads.  A row's cells not computed in this diamond
+// but read by its neighbours are the (at most two) levels just below its first
+// computed level -- or, for a row the end of the run leaves empty, below the
+// level it would have entered at -- and they come from the input pair.
+struct RowDuty {
+    int kv;        // upper duty level (kf-1 when the row computes)
+    bool d1, d2;   // stage kv (from prefetch; rows that compute stage it from
+                   // their input ring instead), stage kv-1
 };
 
 template <class S, typename Real, int DW, int VX>
@@ -225,6 +237,26 @@ mwd_row_kernel(MwdArgs<Real> a) {
     int kfA, klA, kfB, klB;
     row_levels<Sh>(jA, ybase + jA, g.ny, a.t_c, a.T, kfA, klA);
     row_levels<Sh>(jB, ybase + jB, g.ny, a.t_c, a.T, kfB, klB);
+    auto in_layout = [&](int k, int j) -> bool {
+        if (k < 0 || k > L - 2) return false;
+        const int wk = (k + 1) < H ? R * (k + 1) : DW / 2 - R * (k + 1 - H);
+        return j >= DW / 2 - wk - R && j < DW / 2 + wk + R;
+    };
+    auto duty_of = [&](int d, int j, int kf, int kl) -> RowDuty {
+        RowDuty du{-1, false, false};
+        const int64_t y = ybase + j;
+        if (y < 0 || y >= g.ny) return du;
+        const int64_t kmax64 = a.T - 1 + H - a.t_c;   // last level inside the run
+        const int kmax = kmax64 > L - 1 ? L - 1 : (int)kmax64;
+        const int ks = d / R + 1;                      // level the diamond shape enters at
+        du.kv = kf <= kl ? kf - 1 : (ks - 1 < kmax - 1 ? ks - 1 : kmax - 1);
+        auto ok = [&](int k) { return k >= 0 && a.t_c - H + k + 1 >= 0 && in_layout(k, j); };
+        du.d1 = kf > kl && ok(du.kv);
+        du.d2 = ok(du.kv - 1);
+        return du;
+    };
+    const RowDuty uA = duty_of(dA, jA, kfA, klA);
+    const RowDuty uB = duty_of(dB, jB, kfB, klB);
     // The outermost block of rows reads, at level H, the rows up to R beyond
     // the diamond at level H-1 (time t_c).  The owner of an outermost row j
     // stages the row R further out (j+R on the right, j-R on the left); it does
@@ -278,7 +310,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
 #pragma unroll
             for (int v = 0; v < VX; ++v) rr.vring[m][v] = Real(0);
 #pragma unroll
-        for (int v = 0; v < VX; ++v) rr.vnext[v] = rr.pre2[v] = rr.preo[v] = Real(0);
+        for (int v = 0; v < VX; ++v) rr.vnext[v] = rr.pre1[v] = rr.pre2[v] = rr.preo[v] = Real(0);
     };
     zero_regs(RA);
     zero_regs(RB);
@@ -297,19 +329,18 @@ mwd_row_kernel(MwdArgs<Real> a) {
 
     // One-step-ahead loads of a row for step `zs`: the input level kf-1 at the
     // plane it "produces" at that step, and the stage rows of that step.
-    auto prefetch = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, int jo, int64_t zs) {
+    auto prefetch = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, const RowDuty& du, int jo, int64_t zs) {
         if (jo > -1000) load_row(a.in[a.t_c & 1], rowoff(zs - (int64_t)R * H, ybase + jo), rr.preo);
-        if (kf > kl) return;
         const int64_t y = ybase + j;
-        const int64_t s_in = a.t_c - H + kf;     // time level of the entry inputs (>= 0)
-        load_row(a.in[s_in & 1], rowoff(zs - (int64_t)R * (kf - 1), y), rr.vnext);
-        if (kf >= 2 && s_in >= 1)
-            load_row(a.in[(s_in - 1) & 1], rowoff(zs - (int64_t)R * (kf - 1), y), rr.pre2);
+        const int64_t tv = a.t_c - H + du.kv + 1;   // time level of stage duty kv
+        if (kf <= kl) load_row(a.in[tv & 1], rowoff(zs - (int64_t)R * du.kv, y), rr.vnext);
+        if (du.d1) load_row(a.in[tv & 1], rowoff(zs - (int64_t)R * (du.kv + 1), y), rr.pre1);
+        if (du.d2) load_row(a.in[(tv - 1) & 1], rowoff(zs - (int64_t)R * du.kv, y), rr.pre2);
     };
 
     // prologue: loads for step 0
-    prefetch(RA, jA, kfA, klA, joA, 0);
-    prefetch(RB, jB, kfB, klB, joB, 0);
+    prefetch(RA, jA, kfA, klA, uA, joA, 0);
+    prefetch(RB, jB, kfB, klB, uB, joB, 0);
     __syncthreads();
 
     const int64_t nzs = g.nz + (int64_t)R * (L - 1);   // wavefront steps
@@ -340,14 +371,14 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         if (k >= kfb && k <= klb) put_row(srow(k, jb), ringB[i][(ph + RING - R) % RING]);
                     }
                 });
-                auto stage_row = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, int jo) {
+                auto stage_row = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, const RowDuty& du, int jo) {
                     if (jo > -1000) put_row(srow(H - 1, jo), rr.preo);
-                    if (kf > kl) return;
-                    put_row(srow(kf - 1, j), rr.vring[(ph + RING - R) % RING]);
-                    if (kf >= 2) put_row(srow(kf - 2, j), rr.pre2);
+                    if (kf <= kl) put_row(srow(du.kv, j), rr.vring[(ph + RING - R) % RING]);
+                    if (du.d1) put_row(srow(du.kv, j), rr.pre1);
+                    if (du.d2) put_row(srow(du.kv - 1, j), rr.pre2);
                 };
-                stage_row(RA, ja, kfa, kla, opaque_s(joA));
-                stage_row(RB, jb, kfb, klb, opaque_s(joB));
+                stage_row(RA, ja, kfa, kla, uA, opaque_s(joA));
+                stage_row(RB, jb, kfb, klb, uB, opaque_s(joB));
                 // halo rows with a non-zero halo: load them (latency exposed; edge diamonds only)
                 if (edge_y && !zero_halo) {
                     for (int k = wave; k < L - 1; k += KK::NWAVES) {
@@ -362,8 +393,8 @@ mwd_row_kernel(MwdArgs<Real> a) {
                     }
                 }
                 // loads for the next step
-                prefetch(RA, ja, kfa, kla, opaque_s(joA), zs + 1);
-                prefetch(RB, jb, kfb, klb, opaque_s(joB), zs + 1);
+                prefetch(RA, ja, kfa, kla, uA, opaque_s(joA), zs + 1);
+                prefetch(RB, jb, kfb, klb, uB, opaque_s(joB), zs + 1);
             }
             __syncthreads();
             // ---- B: update every owned (row, level) cell of this step ----------
