@@ -338,14 +338,15 @@ mwd_row_kernel(MwdArgs<Real> a) {
         if (du.d2) load_row(a.in[(tv - 1) & 1], rowoff(zs - (int64_t)R * du.kv, y), rr.pre2);
     };
 
-    // prologue: loads for step 0
-    prefetch(RA, jA, kfA, klA, uA, joA, 0);
-    prefetch(RB, jB, kfB, klB, uB, joB, 0);
+    // The sweep starts 2R steps early so that the input rings of rows entering
+    // at level 1 hold the halo planes -R..-1; steps before 0 compute nothing.
+    prefetch(RA, jA, kfA, klA, uA, joA, -RING);
+    prefetch(RB, jB, kfB, klB, uB, joB, -RING);
     __syncthreads();
 
-    const int64_t nzs = g.nz + (int64_t)R * (L - 1);   // wavefront steps
+    const int64_t nzs = g.nz + (int64_t)R * (L - 1);   // wavefront steps end here
 
-    for (int64_t zb = 0; zb < nzs; zb += RING) {
+    for (int64_t zb = -RING; zb < nzs; zb += RING) {
         static_for<0, RING>([&](auto phc) {
             constexpr int ph = decltype(phc)::value;
             const int64_t zs = zb + ph;
@@ -478,7 +479,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 run_row(ringB, std::integral_constant<int, KB_LO>{}, RB, vcurB, opaque_s(jB), opaque_s(kfB),
                         opaque_s(klB));
                 // rows of this diamond with no level in this row: carry both levels
-                if (zs < g.nz) {
+                if (zs >= 0 && zs < g.nz) {
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         const int jr = t == 0 ? jA : jB;
