@@ -167,10 +167,9 @@ struct MwdKernel {
 
 // One-step-ahead registers of an owned row: the cells of earlier diamond rows
 // it needs.
-template <typename Real, int R, int VX>
+template <typename Real, int VX>
 struct RowRegs {
-    Real vring[2 * R][VX];   // z-ring of the input level kf-1 (virtual level)
-    Real vnext[VX];          // input level, plane produced at the coming step
+    Real vnext[VX];          // input level kf-1: plane it "produces" at the coming step
     Real pre1[VX];           // stage duty kv of a row that computes nothing here
     Real pre2[VX];           // stage duty kv-1
     Real preo[VX];           // out-of-span neighbour row for the coming step's stage
@@ -180,12 +179,23 @@ struct RowRegs {
 // t_c-H+k+1 that level k+1 reads.  A row's cells not computed in this diamond
 // but read by its neighbours are the (at most two) levels just below its first
 // computed level -- or, for a row the end of the run leaves empty, below the
-// level it would have entered at -- and they come from the input pair.
+// level it would have entered at -- and they come from the input pair.  A row
+// that computes keeps level kf-1 in the slot of that level (its input ring),
+// fed by the one-step-ahead loads, and stages it like a computed level.
 struct RowDuty {
     int kv;        // upper duty level (kf-1 when the row computes)
-    bool d1, d2;   // stage kv (from prefetch; rows that compute stage it from
-                   // their input ring instead), stage kv-1
+    bool d1, d2;   // stage kv from a prefetch register (rows that compute nothing), stage kv-1
 };
+
+// byte-offset access: uniform row pointer + per-lane 32-bit byte offset
+template <typename Real>
+__device__ __forceinline__ Real ld_at(const Real* row, uint32_t byte_off) {
+    return *reinterpret_cast<const Real*>(reinterpret_cast<const char*>(row) + byte_off);
+}
+template <typename Real>
+__device__ __forceinline__ void st_at(Real* row, uint32_t byte_off, Real v) {
+    *reinterpret_cast<Real*>(reinterpret_cast<char*>(row) + byte_off) = v;
+}
 
 template <class S, typename Real, int DW, int VX>
 __global__ void __launch_bounds__(64 * (DW / 2))
@@ -193,7 +203,9 @@ mwd_row_kernel(MwdArgs<Real> a) {
     using KK = MwdKernel<S, Real, DW, VX>;
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
-    constexpr int NA = Sh::NA, NB = Sh::NB, KB_LO = Sh::KB_LO;
+    constexpr int KB0 = Sh::KB_LO - 1;            // first slot level of row B
+    constexpr int NA = L;                         // row A slots: levels 0..L-1
+    constexpr int NB = Sh::KB_HI - KB0 + 1;       // row B slots: levels KB0..KB_HI
     __shared__ Real stage[Sh::STAGE_ROWS * XLP];
 
     const GridDesc& g = a.g;
@@ -208,14 +220,14 @@ mwd_row_kernel(MwdArgs<Real> a) {
     const bool edge_x = x0 < 0 || x0 + KK::XL > g.nx;          // chunk touches the x halo
     const bool edge_y = ybase - R < 0 || ybase + DW + R > g.ny; // diamond touches the y halo
 
-    // per-lane constants: clamped element offset within a row, ownership, x-halo
-    int xo[VX];
+    // per-lane constants: clamped byte offset within a row, ownership, x-halo
+    uint32_t xb[VX];
     bool own[VX], xh[VX];
 #pragma unroll
     for (int v = 0; v < VX; ++v) {
         const int64_t x = x0 + lane + 64 * v;
         const int64_t xc = x < -R ? -R : (x >= g.nx + R ? g.nx + R - 1 : x);
-        xo[v] = (int)(xc + g.h);
+        xb[v] = (uint32_t)((xc + g.h) * (int64_t)sizeof(Real));
         own[v] = x >= x_own_lo && x < x_own_hi;
         xh[v] = (x >= -R && x < 0) || (x >= g.nx && x < g.nx + R);
     }
@@ -257,6 +269,17 @@ mwd_row_kernel(MwdArgs<Real> a) {
     };
     const RowDuty uA = duty_of(dA, jA, kfA, klA);
     const RowDuty uB = duty_of(dB, jB, kfB, klB);
+    // level bit masks of each row: computed, stored (last two computed), input copied
+    auto bits = [](int lo, int hi) -> uint32_t {
+        return lo > hi ? 0u : (((2u << hi) - 1u) & ~((1u << lo) - 1u));
+    };
+    const uint32_t cmaskA = bits(kfA, klA), cmaskB = bits(kfB, klB);
+    const uint32_t smaskA = bits(kfA > klA - 1 ? kfA : klA - 1, klA);
+    const uint32_t smaskB = bits(kfB > klB - 1 ? kfB : klB - 1, klB);
+    const uint32_t cpmaskA = kfA == klA ? cmaskA : 0u, cpmaskB = kfB == klB ? cmaskB : 0u;
+    // byte offset of row y within a plane (rows of computing slots are inside the grid)
+    const int rowbA = (int)((ybase + jA + g.h) * g.pitch_x * (int64_t)sizeof(Real));
+    const int rowbB = (int)((ybase + jB + g.h) * g.pitch_x * (int64_t)sizeof(Real));
     // The outermost block of rows reads, at level H, the rows up to R beyond
     // the diamond at level H-1 (time t_c).  The owner of an outermost row j
     // stages the row R further out (j+R on the right, j-R on the left); it does
@@ -280,11 +303,18 @@ mwd_row_kernel(MwdArgs<Real> a) {
     auto load_row = [&](const Real* base, int64_t off, Real (&dst)[VX]) {
         const Real* rp = base + off;
 #pragma unroll
-        for (int v = 0; v < VX; ++v) dst[v] = rp[xo[v]];
+        for (int v = 0; v < VX; ++v) dst[v] = ld_at(rp, xb[v]);
     };
+    // Stage a row; with a zero halo the x-halo columns are written as zero here
+    // (their register values are never fixed up on that path).
     auto put_row = [&](Real* sp, const Real (&src)[VX]) {
+        if (edge_x && zero_halo) {
 #pragma unroll
-        for (int v = 0; v < VX; ++v) sp[lane + 64 * v] = src[v];
+            for (int v = 0; v < VX; ++v) sp[lane + 64 * v] = xh[v] ? Real(0) : src[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) sp[lane + 64 * v] = src[v];
+        }
     };
 
     // Halo rows of the stage (rows outside the grid, inside it +-R): with a zero
@@ -301,19 +331,16 @@ mwd_row_kernel(MwdArgs<Real> a) {
         }
     }
 
+    // z-rings: ring[i][m] holds the output of slot i (level K0 + i) at the last
+    // 2R wavefront steps, entry m for steps congruent to m mod 2R.
     Real ringA[NA][RING][VX];
     Real ringB[NB][RING][VX];
-    RowRegs<Real, R, VX> RA, RB;
-    auto zero_regs = [&](RowRegs<Real, R, VX>& rr) {
+    RowRegs<Real, VX> RA, RB;
 #pragma unroll
-        for (int m = 0; m < RING; ++m)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) rr.vring[m][v] = Real(0);
-#pragma unroll
-        for (int v = 0; v < VX; ++v) rr.vnext[v] = rr.pre1[v] = rr.pre2[v] = rr.preo[v] = Real(0);
-    };
-    zero_regs(RA);
-    zero_regs(RB);
+    for (int v = 0; v < VX; ++v) {
+        RA.vnext[v] = RA.pre1[v] = RA.pre2[v] = RA.preo[v] = Real(0);
+        RB.vnext[v] = RB.pre1[v] = RB.pre2[v] = RB.preo[v] = Real(0);
+    }
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
@@ -329,7 +356,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
 
     // One-step-ahead loads of a row for step `zs`: the input level kf-1 at the
     // plane it "produces" at that step, and the stage rows of that step.
-    auto prefetch = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, const RowDuty& du, int jo, int64_t zs) {
+    auto prefetch = [&](RowRegs<Real, VX>& rr, int j, int kf, int kl, const RowDuty& du, int jo, int64_t zs) {
         if (jo > -1000) load_row(a.in[a.t_c & 1], rowoff(zs - (int64_t)R * H, ybase + jo), rr.preo);
         const int64_t y = ybase + j;
         const int64_t tv = a.t_c - H + du.kv + 1;   // time level of stage duty kv
@@ -358,28 +385,28 @@ mwd_row_kernel(MwdArgs<Real> a) {
             if (live) {
                 const int kfa = opaque_s(kfA), kla = opaque_s(klA), kfb = opaque_s(kfB), klb = opaque_s(klB);
                 const int ja = opaque_s(jA), jb = opaque_s(jB);
+                // computed levels and the input level kf-1 of rows that compute
                 static_for<0, NA>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    constexpr int k = 1 + i;
+                    constexpr int k = i;
                     if constexpr (k <= L - 2) {
-                        if (k >= kfa && k <= kla) put_row(srow(k, ja), ringA[i][(ph + RING - R) % RING]);
+                        if (k >= kfa - 1 && k <= kla) put_row(srow(k, ja), ringA[i][(ph + RING - R) % RING]);
                     }
                 });
                 static_for<0, NB>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    constexpr int k = KB_LO + i;
+                    constexpr int k = KB0 + i;
                     if constexpr (k <= L - 2) {
-                        if (k >= kfb && k <= klb) put_row(srow(k, jb), ringB[i][(ph + RING - R) % RING]);
+                        if (k >= kfb - 1 && k <= klb) put_row(srow(k, jb), ringB[i][(ph + RING - R) % RING]);
                     }
                 });
-                auto stage_row = [&](RowRegs<Real, R, VX>& rr, int j, int kf, int kl, const RowDuty& du, int jo) {
+                auto stage_row = [&](RowRegs<Real, VX>& rr, int j, const RowDuty& du, int jo) {
                     if (jo > -1000) put_row(srow(H - 1, jo), rr.preo);
-                    if (kf <= kl) put_row(srow(du.kv, j), rr.vring[(ph + RING - R) % RING]);
                     if (du.d1) put_row(srow(du.kv, j), rr.pre1);
                     if (du.d2) put_row(srow(du.kv - 1, j), rr.pre2);
                 };
-                stage_row(RA, ja, kfa, kla, uA, opaque_s(joA));
-                stage_row(RB, jb, kfb, klb, uB, opaque_s(joB));
+                stage_row(RA, ja, uA, opaque_s(joA));
+                stage_row(RB, jb, uB, opaque_s(joB));
                 // halo rows with a non-zero halo: load them (latency exposed; edge diamonds only)
                 if (edge_y && !zero_halo) {
                     for (int k = wave; k < L - 1; k += KK::NWAVES) {
@@ -400,45 +427,51 @@ mwd_row_kernel(MwdArgs<Real> a) {
             __syncthreads();
             // ---- B: update every owned (row, level) cell of this step ----------
             if (live) {
-                auto run_row = [&](auto& ring, auto kbase_c, RowRegs<Real, R, VX>& rr, const Real (&vcur)[VX],
-                                   int jr, int kf, int kl) {
-                    constexpr int KBASE = decltype(kbase_c)::value;
-                    constexpr int NS = sizeof(ring) / sizeof(ring[0]);
-                    const int64_t y = ybase + jr;
-                    Real prev[VX];   // output of level k-1 at this step (z + R neighbour)
+                // Addresses: every plane a computing slot touches lies in the window
+                // [zs - R*L, zs]; a uniform 64-bit window base per array plus a
+                // 32-bit byte offset (per slot uniform + per lane) reaches it.
+                // The parity of level K's input time level t_c-H+K is p0 ^ (K & 1).
+                const int64_t e0 = (zs - (int64_t)R * L + g.h) * plane;
+                const int p0 = (int)((a.t_c - H) & 1);
+                const Real* in_par[2] = {a.in[p0] + e0, a.in[p0 ^ 1] + e0};
+                Real* out_par[2] = {a.out[p0] + e0, a.out[p0 ^ 1] + e0};
+                const uint32_t plane_b = (uint32_t)(plane * (int64_t)sizeof(Real));
+                // levels whose plane zs - R*K is inside the grid
+                const int64_t khz = zs >= 0 ? zs / R : -1;
+                const int64_t klz = zs - g.nz >= 0 ? (zs - g.nz) / R + 1 : 0;
+                const uint32_t zmask = khz < klz ? 0u
+                    : ((khz >= 31 ? 0xffffffffu : ((2u << khz) - 1u)) & ~((1u << (klz > 31 ? 31 : klz)) - 1u));
+                // One slot of one row: levels kf..kl compute, every other slot
+                // passes the loaded input plane on (the input level kf-1 keeps it
+                // in its ring).  prev is the slot below's output at this step (the
+                // z+R neighbour); the slot below's ring is updated only after this
+                // slot has read it.
+                auto slot = [&](auto ic, auto k0c, auto& ring, Real (&prev)[VX], const Real (&vcur)[VX],
+                                const Real* st_row, uint32_t rowb, uint32_t cmask, uint32_t smask,
+                                uint32_t cpmask, int64_t y) {
+                    constexpr int i = decltype(ic)::value;
+                    constexpr int K = decltype(k0c)::value + i;
+                    constexpr int KP = K & 1;
+                    Real nv[VX];
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) prev[v] = vcur[v];
-                    static_for<0, NS>([&](auto ic) {
-                        constexpr int i = decltype(ic)::value;
-                        constexpr int K = KBASE + i;
-                        Real nv[VX];
-#pragma unroll
-                        for (int v = 0; v < VX; ++v) nv[v] = Real(0);
-                        if (K >= kf && K <= kl) {
-                            const int64_t q = opaque_s(zs) - (int64_t)R * K;
-                            const bool entry = K == kf;
-                            // z-window of level K-1: ring of slot i-1, or the input ring
-                            Real zw[RING][VX];
-#pragma unroll
-                            for (int m = 0; m < RING; ++m)
-#pragma unroll
-                                for (int v = 0; v < VX; ++v) {
-                                    if constexpr (i == 0) zw[m][v] = rr.vring[m][v];
-                                    else zw[m][v] = entry ? rr.vring[m][v] : ring[i - 1][m][v];
-                                }
-                            if (q >= 0 && q < g.nz) {
-                                const int64_t s_in = a.t_c - H + K;          // input time level
-                                const int64_t ro = rowoff(q, y);
-                                const Real* st = srow(K - 1, jr);
+                    for (int v = 0; v < VX; ++v) nv[v] = vcur[v];
+                    if constexpr (i > 0) {
+                        if ((cmask >> K) & 1u) {
+                            if ((zmask >> K) & 1u) {
+                                const uint32_t so = (uint32_t)(R * (L - K)) * plane_b + rowb;
+                                const Real* st = st_row + Sh::srow0(K - 1) * XLP;
+                                const bool cpy = (cpmask >> K) & 1u;
+                                Real cin[VX];
 #pragma unroll
                                 for (int v = 0; v < VX; ++v) {
                                     const int col = lane + 64 * v;
+                                    const uint32_t vo = so + xb[v];
                                     Nbhd<Real, R> n;
-                                    n.c = zw[(ph + R) % RING][v];
+                                    n.c = ring[i - 1][(ph + R) % RING][v];
 #pragma unroll
                                     for (int r = 1; r <= R; ++r) {
-                                        n.zm[r - 1] = zw[(ph + R - r) % RING][v];
-                                        n.zp[r - 1] = r == R ? prev[v] : zw[(ph + R + r) % RING][v];
+                                        n.zm[r - 1] = ring[i - 1][(ph + R - r) % RING][v];
+                                        n.zp[r - 1] = r == R ? prev[v] : ring[i - 1][(ph + R + r) % RING][v];
                                         n.xp[r - 1] = st[col + r];
                                         n.xm[r - 1] = st[col - r];
                                         n.yp[r - 1] = st[col + r * XLP];
@@ -446,38 +479,66 @@ mwd_row_kernel(MwdArgs<Real> a) {
                                     }
                                     Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
 #pragma unroll
-                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = a.coef.arr[m][ro + xo[v]];
-                                    Real u = S::apply(n, a.coef.k, cf);
-                                    if (edge_x && xh[v]) u = zero_halo ? Real(0) : a.in[0][ro + xo[v]];
-                                    nv[v] = u;
-                                    if (own[v]) {
-                                        if (K >= kl - 1) a.out[(s_in + 1) & 1][ro + xo[v]] = u;
-                                        if (kf == kl) a.out[s_in & 1][ro + xo[v]] = n.c;
-                                    }
+                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = ld_at(a.coef.arr[m] + e0, vo);
+                                    nv[v] = S::apply(n, a.coef.k, cf);
+                                    if (cpy) cin[v] = n.c;
                                 }
-                            } else if (!zero_halo && q >= -R && q < g.nz + R) {
-                                load_row(a.in[0], rowoff(q, y), nv);   // fixed halo plane
+                                // x-halo lanes hold the fixed halo (a zero halo is
+                                // written into the stage instead, see put_row)
+                                if (edge_x && !zero_halo) {
+#pragma unroll
+                                    for (int v = 0; v < VX; ++v)
+                                        if (xh[v]) nv[v] = ld_at(in_par[0], so + xb[v]);
+                                }
+                                // the last two levels of a row go to the output pair
+                                if ((smask >> K) & 1u) {
+#pragma unroll
+                                    for (int v = 0; v < VX; ++v)
+                                        if (own[v]) st_at(out_par[KP ^ 1], so + xb[v], nv[v]);
+                                }
+                                if (cpy) {
+#pragma unroll
+                                    for (int v = 0; v < VX; ++v)
+                                        if (own[v]) st_at(out_par[KP], so + xb[v], cin[v]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int v = 0; v < VX; ++v) nv[v] = Real(0);
+                                const int64_t q = zs - (int64_t)R * K;
+                                if (!zero_halo && q >= -R && q < g.nz + R)
+                                    load_row(a.in[0], rowoff(q, y), nv);   // fixed halo plane
                             }
                         }
-                        if constexpr (i > 0) {
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) ring[i - 1][ph][v] = prev[v];
-                        }
-                        // prev stays the input level's output until the row's first level
-                        if (K >= kf && K <= kl) {
+                        for (int v = 0; v < VX; ++v) ring[i - 1][ph][v] = prev[v];
+                    }
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) prev[v] = nv[v];
-                        }
-                    });
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) ring[NS - 1][ph][v] = prev[v];
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) rr.vring[ph][v] = vcur[v];
+                    for (int v = 0; v < VX; ++v) prev[v] = nv[v];
                 };
-                run_row(ringA, std::integral_constant<int, 1>{}, RA, vcurA, opaque_s(jA), opaque_s(kfA),
-                        opaque_s(klA));
-                run_row(ringB, std::integral_constant<int, KB_LO>{}, RB, vcurB, opaque_s(jB), opaque_s(kfB),
-                        opaque_s(klB));
+                Real prevA[VX], prevB[VX];
+#pragma unroll
+                for (int v = 0; v < VX; ++v) { prevA[v] = vcurA[v]; prevB[v] = vcurB[v]; }
+                const Real* stA = stage + opaque_s(jA) * XLP + R;
+                const Real* stB = stage + opaque_s(jB) * XLP + R;
+                const uint32_t rbA = (uint32_t)opaque_s(rowbA), rbB = (uint32_t)opaque_s(rowbB);
+                const uint32_t cmA = (uint32_t)opaque_s((int)cmaskA), cmB = (uint32_t)opaque_s((int)cmaskB);
+                const uint32_t smA = (uint32_t)opaque_s((int)smaskA), smB = (uint32_t)opaque_s((int)smaskB);
+                const uint32_t cpA = (uint32_t)opaque_s((int)cpmaskA), cpB = (uint32_t)opaque_s((int)cpmaskB);
+                // interleave the two rows level by level: two independent chains
+                static_for<0, NA>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    slot(ic, std::integral_constant<int, 0>{}, ringA, prevA, vcurA, stA, rbA, cmA, smA, cpA,
+                         ybase + jA);
+                    if constexpr (i >= KB0 && i - KB0 < NB) {
+                        slot(std::integral_constant<int, i - KB0>{}, std::integral_constant<int, KB0>{}, ringB, prevB,
+                             vcurB, stB, rbB, cmB, smB, cpB, ybase + jB);
+                    }
+                });
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    ringA[NA - 1][ph][v] = prevA[v];
+                    ringB[NB - 1][ph][v] = prevB[v];
+                }
                 // rows of this diamond with no level in this row: carry both levels
                 if (zs >= 0 && zs < g.nz) {
 #pragma unroll
@@ -490,8 +551,8 @@ mwd_row_kernel(MwdArgs<Real> a) {
 #pragma unroll
                             for (int v = 0; v < VX; ++v) {
                                 if (own[v]) {
-                                    a.out[0][ro + xo[v]] = a.in[0][ro + xo[v]];
-                                    a.out[1][ro + xo[v]] = a.in[1][ro + xo[v]];
+                                    st_at(a.out[0] + ro, xb[v], ld_at(a.in[0] + ro, xb[v]));
+                                    st_at(a.out[1] + ro, xb[v], ld_at(a.in[1] + ro, xb[v]));
                                 }
                             }
                         }
