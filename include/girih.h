@@ -57,6 +57,9 @@ typedef enum {
     GIRIH_NAIVE = 0, /* T launches of one full-domain Jacobi step              */
     GIRIH_MWD = 1    /* diamond rows: one launch per row of diamond tiles      */
 } girih_algo;
+/* This version provides GIRIH_MWD for the constant-coefficient stencils
+ * (GIRIH_7PT_CONST, GIRIH_25PT_CONST); girih_plan returns GIRIH_E_UNSUPPORTED
+ * for GIRIH_MWD with a variable-coefficient stencil. */
 
 /* Grid descriptor, in elements. */
 typedef struct girih_grid {
@@ -71,9 +74,11 @@ typedef struct girih_grid {
  *  MWD:   diamond_width  Dw, multiple of 2R (of 4 when R = 1);
  *         wavefront_depth N_F, z-planes per wavefront step (1);
  *         tile_x         x cells one workgroup owns and stores;
- *         threads_x      x cells one wave holds per row = 64 * cells per lane
- *                        (64, 128 or 256);
- *         threads_y      waves per workgroup (filled in: Dw/2);
+ *         threads_x      threads along x per diamond row = 64 * waves along x;
+ *         cells_per_lane x cells each of those threads holds (1, 2, 4): a row
+ *                        of the workgroup spans threads_x * cells_per_lane
+ *                        cells, owned tile plus the recomputed halo;
+ *         threads_y      row pairs = waves along y (filled in: Dw/2);
  *         tile_y, tile_z filled in: Dw and nz;
  *         variant        0 = barrier per wavefront step.
  *  NAIVE: threads_x, threads_y  block shape (x lanes, y rows);
@@ -87,6 +92,7 @@ typedef struct girih_params {
     int32_t threads_x;
     int32_t threads_y;
     int32_t variant;
+    int32_t cells_per_lane;
 } girih_params;
 
 typedef struct girih_plan_s* girih_plan_t;

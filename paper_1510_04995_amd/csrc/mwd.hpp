@@ -150,29 +150,24 @@ __host__ __device__ inline void row_levels(int j, int64_t y, int64_t ny, int64_t
     kf = (int)lo; kl = (int)hi;
 }
 
-template <class S, typename Real, int DW, int VX>
+template <class S, typename Real, int DW, int VX, int WX>
 struct MwdKernel {
     static constexpr int R = S::R;
     using Sh = DiamondShape<R, DW>;
     static constexpr int H = Sh::H, L = Sh::L;
-    static constexpr int NWAVES = DW / 2;
+    static constexpr int NPAIRS = DW / 2;       // waves along y (row pairs)
+    static constexpr int NWAVES = NPAIRS * WX;  // WX waves along x per row pair
     static constexpr int NT = 64 * NWAVES;
-    static constexpr int XL = 64 * VX;          // x cells held per row
+    static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
+    static constexpr int XL = 64 * VX * WX;     // x cells held per row
     static constexpr int XLP = XL + 2 * R;      // LDS row stride (R guard cells per side)
     static constexpr int HX = R * (L - 1);      // redundant x halo per side
     static constexpr int XOWN_MAX = XL - 2 * HX;
-    static constexpr int LDS_BYTES = Sh::STAGE_ROWS * XLP * (int)sizeof(Real);
+    // stage rows plus 2R+1 spare rows that absorb the stage writes and reads of
+    // slots without a stage row
+    static constexpr int LDS_ROWS = Sh::STAGE_ROWS + 2 * R + 1;
+    static constexpr int LDS_BYTES = LDS_ROWS * XLP * (int)sizeof(Real);
     static constexpr int RING = 2 * R;
-};
-
-// One-step-ahead registers of an owned row: the cells of earlier diamond rows
-// it needs.
-template <typename Real, int VX>
-struct RowRegs {
-    Real vnext[VX];          // input level kf-1: plane it "produces" at the coming step
-    Real pre1[VX];           // stage duty kv of a row that computes nothing here
-    Real pre2[VX];           // stage duty kv-1
-    Real preo[VX];           // out-of-span neighbour row for the coming step's stage
 };
 
 // Stage duties of one owned row.  Level k of the stage holds the time level
@@ -181,7 +176,7 @@ struct RowRegs {
 // computed level -- or, for a row the end of the run leaves empty, below the
 // level it would have entered at -- and they come from the input pair.  A row
 // that computes keeps level kf-1 in the slot of that level (its input ring),
-// fed by the one-step-ahead loads, and stages it like a computed level.
+// fed by one-step-ahead loads, and stages it like a computed level.
 struct RowDuty {
     int kv;        // upper duty level (kf-1 when the row computes)
     bool d1, d2;   // stage kv from a prefetch register (rows that compute nothing), stage kv-1
@@ -197,45 +192,129 @@ __device__ __forceinline__ void st_at(Real* row, uint32_t byte_off, Real v) {
     *reinterpret_cast<Real*>(reinterpret_cast<char*>(row) + byte_off) = v;
 }
 
-template <class S, typename Real, int DW, int VX>
-__global__ void __launch_bounds__(64 * (DW / 2))
+// Closed form of DiamondShape::srow0 for a level known only at run time.
+template <class Sh>
+__device__ __forceinline__ int srow0_rt(int k) {
+    constexpr int R = Sh::R, H = Sh::H, DW = Sh::DW;
+    const int base = k <= H ? R * k * (k + 3) : R * H * (H + 3) + (k - H) * DW - R * (k - H) * (k - H - 1);
+    const int w1 = (k + 1) < H ? R * (k + 1) : DW / 2 - R * (k + 1 - H);
+    return base - (DW / 2 - w1 - R);
+}
+
+// A wave-uniform value held in a vector register (keeps scalar registers free
+// for what must be scalar).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t s) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+// A wave-uniform value the compiler must treat as changed at this point, so
+// that tests of its bits are made where they are used instead of being
+// hoisted out of the wavefront loop as per-slot lane masks.
+__device__ __forceinline__ uint32_t fresh_s(uint32_t x) {
+    x = __builtin_amdgcn_readfirstlane(x);
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// Same for a per-lane value: derived values are recomputed where used rather
+// than precomputed per slot and kept alive (or spilled) across the loop.
+__device__ __forceinline__ uint32_t fresh_v(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Buffer resource of a raw byte range starting at p (stride 0, 2^31 - 1
+// bytes): stores whose offset is 2^31 or more fall outside the range and are
+// dropped by the hardware's range check.
+constexpr uint32_t DROP = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, 0x7fffffff, 0x00020000);
+}
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, off, 0, 0);
+}
+
+// Bits lo..hi of a 32-bit mask (empty if lo > hi), clamped to 0..31.
+__device__ __forceinline__ uint32_t bit_range(int lo, int hi) {
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > 31 ? 31 : hi;
+    return lo > hi ? 0u : (((2u << hi) - 1u) & ~((1u << lo) - 1u));
+}
+
+// Flag bits of a wave's scalar state.
+enum : int {
+    F_IN_A = 1 << 0, F_IN_B = 1 << 1,           // row inside the grid
+    F_EDGE_X = 1 << 2, F_EDGE_Y = 1 << 3,       // workgroup touches the x / y halo
+    F_CMP_A = 1 << 5, F_CMP_B = 1 << 6,         // row computes at least one level
+    F_D1_A = 1 << 7, F_D2_A = 1 << 8, F_D1_B = 1 << 9, F_D2_B = 1 << 10,   // stage duties
+    F_O_A = 1 << 11, F_O_B = 1 << 12,           // out-of-span duty
+    F_PV_A = 1 << 13, F_PV_B = 1 << 14,         // parity of duty level kv's time level
+    F_PT = 1 << 15                              // parity of t_c
+};
+
+// Every wave runs the same code: its two rows are laid out as one list of at
+// most NS = L + 2 register slots -- row A's input level kfA-1 and its computed
+// levels kfA..klA, then row B's input level and levels (a row that computes
+// nothing keeps one unused slot).  A slot's level, LDS row and global offset
+// are fixed per wave and precomputed; the ring of slot s (the last 2R planes
+// of its level) lives in registers at a compile-time index.  Slots without a
+// stage row of their own (unused slots, level L-1) write and read a block of
+// spare LDS rows.  For R = 1 the two ring phases are unrolled (renaming); for
+// larger R the rings shift by one register per step, which keeps the loop
+// body small enough for the instruction cache.
+//
+// Two bodies share this state: the general one (any wavefront step) and the
+// steady one, for steps at which the plane of every level lies inside the
+// grid: it computes every slot without tests (unused slots compute values
+// nobody reads) and keeps scalar work per step to a few tests.
+template <class S, typename Real, int DW, int VX, int WX>
+__global__ void __launch_bounds__(64 * (DW / 2) * WX)
 mwd_row_kernel(MwdArgs<Real> a) {
-    using KK = MwdKernel<S, Real, DW, VX>;
+    using KK = MwdKernel<S, Real, DW, VX, WX>;
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
-    constexpr int KB0 = Sh::KB_LO - 1;            // first slot level of row B
-    constexpr int NA = L;                         // row A slots: levels 0..L-1
-    constexpr int NB = Sh::KB_HI - KB0 + 1;       // row B slots: levels KB0..KB_HI
-    __shared__ Real stage[Sh::STAGE_ROWS * XLP];
+    constexpr int NS = L + 2;
+    constexpr int UNR = RING <= 2 ? RING : 1;
+    constexpr int SB = (int)sizeof(Real);
+    static_assert(NS <= 32, "slot masks are 32-bit");
+    __shared__ Real stage[KK::LDS_ROWS * XLP];
 
-    const GridDesc& g = a.g;
+    // ---- geometry (32-bit: sizes are bounded by the planner) ----------------
+    const int nx = (int)a.g.nx, ny = (int)a.g.ny, nz = (int)a.g.nz, hh = a.g.h;
+    const int pitchx = (int)a.g.pitch_x;
+    const uint32_t plane_b = (uint32_t)(a.g.plane() * SB);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const int64_t c = a.c_first + (int64_t)blockIdx.y * DW;     // diamond centre (global y)
-    const int64_t ybase = c - DW / 2;                           // global y of local row 0
-    const int64_t x_own_lo = (int64_t)blockIdx.x * a.x_own;
-    const int64_t x_own_hi = x_own_lo + a.x_own < g.nx ? x_own_lo + a.x_own : g.nx;
-    const int64_t x0 = x_own_lo - KK::HX;                       // x of column 0
-    const int zero_halo = __builtin_amdgcn_readfirstlane(*a.zero_halo);
-    const bool edge_x = x0 < 0 || x0 + KK::XL > g.nx;          // chunk touches the x halo
-    const bool edge_y = ybase - R < 0 || ybase + DW + R > g.ny; // diamond touches the y halo
+    const int pw = wave % KK::NPAIRS;              // row pair of this wave
+    const int cb = 64 * VX * (wave / KK::NPAIRS);  // first column of this wave's x slice
+    const int ybase = (int)(a.c_first + (int64_t)blockIdx.y * DW) - DW / 2;   // global y of local row 0
+    const int x_own_lo = (int)blockIdx.x * a.x_own;
+    const int x_own_hi = x_own_lo + a.x_own < nx ? x_own_lo + a.x_own : nx;
+    const int x0 = x_own_lo - KK::HX;              // x of column 0
+    const int t_c = (int)a.t_c, T = (int)a.T;
 
     // per-lane constants: clamped byte offset within a row, ownership, x-halo
-    uint32_t xb[VX];
-    bool own[VX], xh[VX];
+    uint32_t xb[VX], kill[VX];   // kill: DROP on lanes whose stores this chunk does not own
+    bool xh[VX];
 #pragma unroll
     for (int v = 0; v < VX; ++v) {
-        const int64_t x = x0 + lane + 64 * v;
-        const int64_t xc = x < -R ? -R : (x >= g.nx + R ? g.nx + R - 1 : x);
-        xb[v] = (uint32_t)((xc + g.h) * (int64_t)sizeof(Real));
-        own[v] = x >= x_own_lo && x < x_own_hi;
-        xh[v] = (x >= -R && x < 0) || (x >= g.nx && x < g.nx + R);
+        const int x = x0 + cb + lane + 64 * v;
+        const int xc = x < -R ? -R : (x >= nx + R ? nx + R - 1 : x);
+        xb[v] = (uint32_t)((xc + hh) * SB);
+        kill[v] = x >= x_own_lo && x < x_own_hi ? 0u : DROP;
+        xh[v] = (x >= -R && x < 0) || (x >= nx && x < nx + R);
     }
 
     // ---- this wave's two rows ------------------------------------------------
     const int per_side = DW / 4;
-    const int side = wave / per_side;       // 0: right half (j >= DW/2), 1: left half
-    int p = wave % per_side;
+    const int side = pw / per_side;         // 0: right half (j >= DW/2), 1: left half
+    int p = pw % per_side;
     int dA = 0, dB = 0;
     for (int d = 0; d < DW / 2; ++d) {
         const int pd = partner_of<Sh>(d);
@@ -247,312 +326,378 @@ mwd_row_kernel(MwdArgs<Real> a) {
     const int jA = side == 0 ? DW / 2 + dA : DW / 2 - 1 - dA;
     const int jB = side == 0 ? DW / 2 + dB : DW / 2 - 1 - dB;
     int kfA, klA, kfB, klB;
-    row_levels<Sh>(jA, ybase + jA, g.ny, a.t_c, a.T, kfA, klA);
-    row_levels<Sh>(jB, ybase + jB, g.ny, a.t_c, a.T, kfB, klB);
+    row_levels<Sh>(jA, ybase + jA, ny, t_c, T, kfA, klA);
+    row_levels<Sh>(jB, ybase + jB, ny, t_c, T, kfB, klB);
     auto in_layout = [&](int k, int j) -> bool {
         if (k < 0 || k > L - 2) return false;
         const int wk = (k + 1) < H ? R * (k + 1) : DW / 2 - R * (k + 1 - H);
         return j >= DW / 2 - wk - R && j < DW / 2 + wk + R;
     };
-    auto duty_of = [&](int d, int j, int kf, int kl) -> RowDuty {
-        RowDuty du{-1, false, false};
-        const int64_t y = ybase + j;
-        if (y < 0 || y >= g.ny) return du;
-        const int64_t kmax64 = a.T - 1 + H - a.t_c;   // last level inside the run
-        const int kmax = kmax64 > L - 1 ? L - 1 : (int)kmax64;
+    // Stage duties of a row: levels kv (from the input ring when the row
+    // computes, else from a prefetch register) and kv-1.
+    auto duty_of = [&](int d, int j, int kf, int kl, int& kv, bool& d1, bool& d2) {
+        kv = -1; d1 = d2 = false;
+        const int y = ybase + j;
+        if (y < 0 || y >= ny) return;
+        const int kmax = T - 1 + H - t_c > L - 1 ? L - 1 : T - 1 + H - t_c;   // last level inside the run
         const int ks = d / R + 1;                      // level the diamond shape enters at
-        du.kv = kf <= kl ? kf - 1 : (ks - 1 < kmax - 1 ? ks - 1 : kmax - 1);
-        auto ok = [&](int k) { return k >= 0 && a.t_c - H + k + 1 >= 0 && in_layout(k, j); };
-        du.d1 = kf > kl && ok(du.kv);
-        du.d2 = ok(du.kv - 1);
-        return du;
+        kv = kf <= kl ? kf - 1 : (ks - 1 < kmax - 1 ? ks - 1 : kmax - 1);
+        auto ok = [&](int k) { return k >= 0 && t_c - H + k + 1 >= 0 && in_layout(k, j); };
+        d1 = kf > kl && ok(kv);
+        d2 = ok(kv - 1);
     };
-    const RowDuty uA = duty_of(dA, jA, kfA, klA);
-    const RowDuty uB = duty_of(dB, jB, kfB, klB);
-    // level bit masks of each row: computed, stored (last two computed), input copied
-    auto bits = [](int lo, int hi) -> uint32_t {
-        return lo > hi ? 0u : (((2u << hi) - 1u) & ~((1u << lo) - 1u));
-    };
-    const uint32_t cmaskA = bits(kfA, klA), cmaskB = bits(kfB, klB);
-    const uint32_t smaskA = bits(kfA > klA - 1 ? kfA : klA - 1, klA);
-    const uint32_t smaskB = bits(kfB > klB - 1 ? kfB : klB - 1, klB);
-    const uint32_t cpmaskA = kfA == klA ? cmaskA : 0u, cpmaskB = kfB == klB ? cmaskB : 0u;
-    // byte offset of row y within a plane (rows of computing slots are inside the grid)
-    const int rowbA = (int)((ybase + jA + g.h) * g.pitch_x * (int64_t)sizeof(Real));
-    const int rowbB = (int)((ybase + jB + g.h) * g.pitch_x * (int64_t)sizeof(Real));
+    int kvA, kvB;
+    bool d1A, d2A, d1B, d2B;
+    duty_of(dA, jA, kfA, klA, kvA, d1A, d2A);
+    duty_of(dB, jB, kfB, klB, kvB, d1B, d2B);
     // The outermost block of rows reads, at level H, the rows up to R beyond
     // the diamond at level H-1 (time t_c).  The owner of an outermost row j
     // stages the row R further out (j+R on the right, j-R on the left); it does
     // so whether or not its own row is inside the grid.
     auto out_row = [&](int d, int j) -> int {
-        if (d / R != H - 1 || a.t_c >= a.T) return -1000;
+        if (d / R != H - 1 || t_c >= T) return -1000;
         const int jo = side == 0 ? j + R : j - R;
-        const int64_t yo = ybase + jo;
-        return yo >= -R && yo < g.ny + R ? jo : -1000;
+        const int yo = ybase + jo;
+        return yo >= -R && yo < ny + R ? jo : -1000;
     };
-    const int joA = out_row(dA, jA);
-    const int joB = out_row(dB, jB);
+    const int joA = out_row(dA, jA), joB = out_row(dB, jB);
+    const bool inA = ybase + jA >= 0 && ybase + jA < ny, inB = ybase + jB >= 0 && ybase + jB < ny;
+    const bool cmpA = kfA <= klA, cmpB = kfB <= klB;
+    const bool edge_x = x0 < 0 || x0 + KK::XL > nx;           // chunk touches the x halo
+    const bool edge_y = ybase - R < 0 || ybase + DW + R > ny;  // diamond touches the y halo
+    const int zero_halo = __builtin_amdgcn_readfirstlane(*a.zero_halo);
+    const int p0 = (t_c - H) & 1;   // parity of the time level of level 0
+    const int flags = (inA ? F_IN_A : 0) | (inB ? F_IN_B : 0) | (edge_x ? F_EDGE_X : 0) |
+                      (edge_y ? F_EDGE_Y : 0) | (cmpA ? F_CMP_A : 0) |
+                      (cmpB ? F_CMP_B : 0) | (d1A ? F_D1_A : 0) | (d2A ? F_D2_A : 0) | (d1B ? F_D1_B : 0) |
+                      (d2B ? F_D2_B : 0) | (joA > -1000 ? F_O_A : 0) | (joB > -1000 ? F_O_B : 0) |
+                      (((t_c - H + kvA + 1) & 1) ? F_PV_A : 0) | (((t_c - H + kvB + 1) & 1) ? F_PV_B : 0) |
+                      ((t_c & 1) ? F_PT : 0);
+    auto rowb_of = [&](int j) -> uint32_t { return (uint32_t)((ybase + j + hh) * pitchx * SB); };
+    auto lds_row = [&](int k, int j) -> int { return (srow0_rt<Sh>(k) + j) * XLP + R; };   // element index
+    const uint32_t lane_b = (uint32_t)((cb + lane) * SB);
+    // per-lane LDS byte addresses of the duty rows
+    auto lds_addr = [&](int k, int j) -> uint32_t { return in_vgpr((uint32_t)(lds_row(k, j) * SB)) + lane_b; };
+    const uint32_t lA1 = lds_addr(kvA, jA), lA2 = lds_addr(kvA - 1, jA), lB1 = lds_addr(kvB, jB),
+                   lB2 = lds_addr(kvB - 1, jB), lOA = lds_addr(H - 1, joA), lOB = lds_addr(H - 1, joB);
+    // Per-lane byte offsets of the prefetch streams from the base of the next
+    // step's window (plane zs + 1 - R*L): a stream at depth dz reads plane
+    // zs + 1 - R*dz of its row.
+    auto fo_of = [&](int dz, int j, uint32_t (&o)[VX]) {
+        const uint32_t u = in_vgpr((uint32_t)(R * (L - dz)) * plane_b + rowb_of(j));
+#pragma unroll
+        for (int v = 0; v < VX; ++v) o[v] = u + xb[v];
+    };
+    uint32_t foA[VX], foA1[VX], foB[VX], foB1[VX], foOA[VX], foOB[VX];
+    fo_of(kvA < 0 ? 0 : kvA, jA, foA);
+    fo_of(kvA < 0 ? 0 : kvA + 1, jA, foA1);
+    fo_of(kvB < 0 ? 0 : kvB, jB, foB);
+    fo_of(kvB < 0 ? 0 : kvB + 1, jB, foB1);
+    fo_of(H, joA > -1000 ? joA : jA, foOA);
+    fo_of(H, joB > -1000 ? joB : jB, foOB);
 
-    const int64_t plane = g.plane();
-    // element offset of (plane q, global row y); q clamped into the haloed box
-    auto rowoff = [&](int64_t q, int64_t y) -> int64_t {
-        q = q < -R ? -R : (q >= g.nz + R ? g.nz + R - 1 : q);
-        return (q + g.h) * plane + (y + g.h) * g.pitch_x;
-    };
-    auto srow = [&](int k, int j) -> Real* { return stage + (Sh::srow0(k) + j) * XLP + R; };
-    auto load_row = [&](const Real* base, int64_t off, Real (&dst)[VX]) {
-        const Real* rp = base + off;
-#pragma unroll
-        for (int v = 0; v < VX; ++v) dst[v] = ld_at(rp, xb[v]);
-    };
-    // Stage a row; with a zero halo the x-halo columns are written as zero here
-    // (their register values are never fixed up on that path).
-    auto put_row = [&](Real* sp, const Real (&src)[VX]) {
-        if (edge_x && zero_halo) {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) sp[lane + 64 * v] = xh[v] ? Real(0) : src[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) sp[lane + 64 * v] = src[v];
-        }
-    };
+    // ---- slot layout -----------------------------------------------------------
+    const int sB = cmpA ? klA - kfA + 2 : 1;   // first slot of row B
+    const int nB = cmpB ? klB - kfB + 2 : 1;
+    const int baseA = kfA - 1, baseB = kfB - 1;   // level of each row's first slot
+    // LDS byte address (per lane) of the corner (row - R, column - R) of the
+    // slot's stage row, and the slot's global byte offset within the step's
+    // window (plane of its level, its row); masks over slots.
+    constexpr int CORNER = (R * XLP + R) * SB;   // from the corner to the cell itself
+    const uint32_t spare = (uint32_t)(Sh::STAGE_ROWS * XLP * SB);
+    uint32_t lcs[NS], gos[NS];
+    uint32_t cmS = 0, stoS = 0, stcS = 0, parS = 0;
+    static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
+        const bool isB = s >= sB;
+        const int t = isB ? s - sB : s;
+        const bool valid = isB ? (cmpB && t < nB) : cmpA;
+        const int k = (isB ? baseB : baseA) + t;
+        const int j = isB ? jB : jA;
+        const int kf = isB ? kfB : kfA, kl = isB ? klB : klA;
+        lcs[s] = in_vgpr(valid && k <= L - 2 ? (uint32_t)(lds_row(k, j) * SB - CORNER) : spare) + lane_b;
+        gos[s] = in_vgpr(valid ? (uint32_t)(R * (L - k)) * plane_b + rowb_of(j) : 0u);
+        const bool cmp = valid && t >= 1;
+        cmS |= cmp ? 1u << s : 0u;
+        stoS |= cmp && k >= kl - 1 ? 1u << s : 0u;
+        stcS |= cmp && kf == kl ? 1u << s : 0u;
+        parS |= ((p0 ^ k ^ 1) & 1) ? 1u << s : 0u;
+    });
+    const uint32_t maskA = bit_range(0, sB - 1);
 
-    // Halo rows of the stage (rows outside the grid, inside it +-R): with a zero
-    // halo they are written once here and never touched again.
-    if (edge_y && zero_halo) {
-        for (int k = 0; k < L - 1; ++k) {
-            for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
-                const int64_t y = ybase + j;
-                if ((y >= -R && y < 0) || (y >= g.ny && y < g.ny + R)) {
-                    Real* sp = srow(k, j) - R;
-                    for (int col = threadIdx.x; col < XLP; col += KK::NT) sp[col] = Real(0);
+    // Two instances of the sweep: zero Dirichlet halo (halo cells are
+    // constants) and general halo (loaded where needed).
+    auto sweep = [&](auto zhc) __attribute__((always_inline)) {
+        constexpr bool ZH = decltype(zhc)::value;
+        // Halo rows of the stage (rows outside the grid, inside it +-R): with a zero
+        // halo they are written once here and never touched again.
+        if (ZH && edge_y) {
+            for (int k = 0; k < L - 1; ++k) {
+                for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
+                    const int y = ybase + j;
+                    if ((y >= -R && y < 0) || (y >= ny && y < ny + R)) {
+                        Real* sp = stage + lds_row(k, j) - R;
+                        for (int col = threadIdx.x; col < XLP; col += KK::NT) sp[col] = Real(0);
+                    }
                 }
             }
         }
-    }
+        // x-halo lanes staged as zero when the halo is zero
+        bool hz[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) hz[v] = ZH && edge_x && xh[v];
 
-    // z-rings: ring[i][m] holds the output of slot i (level K0 + i) at the last
-    // 2R wavefront steps, entry m for steps congruent to m mod 2R.
-    Real ringA[NA][RING][VX];
-    Real ringB[NB][RING][VX];
-    RowRegs<Real, VX> RA, RB;
+        const int nzs = nz + R * (L - 1);   // wavefront steps end here
+        // byte offset of plane q from the array base
+        auto plane_off = [&](int q) -> int64_t { return (int64_t)(q + hh) * (int64_t)plane_b; };
+        auto at = [](const Real* base, int64_t off) -> const Real* {
+            return reinterpret_cast<const Real*>(reinterpret_cast<const char*>(base) + off);
+        };
+        auto atw = [](Real* base, int64_t off) -> Real* {
+            return reinterpret_cast<Real*>(reinterpret_cast<char*>(base) + off);
+        };
+        auto lds = [&](uint32_t byte_addr) -> Real& {
+            return *reinterpret_cast<Real*>(reinterpret_cast<char*>(stage) + byte_addr);
+        };
+        auto put = [&](uint32_t la, const Real (&src)[VX]) {   // la: per-lane LDS byte address
 #pragma unroll
-    for (int v = 0; v < VX; ++v) {
-        RA.vnext[v] = RA.pre1[v] = RA.pre2[v] = RA.preo[v] = Real(0);
-        RB.vnext[v] = RB.pre1[v] = RB.pre2[v] = RB.preo[v] = Real(0);
-    }
+            for (int v = 0; v < VX; ++v) lds(la + 64 * v * SB) = hz[v] ? Real(0) : src[v];
+        };
+        // x-halo columns of a staged computed row when the halo is not zero
+        auto fix_halo_cols = [&](int li, int q, int y) {
+            if (q < -R || q >= nz + R) return;
+            const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int m = 0; m < RING; ++m)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) ringA[i][m][v] = Real(0);
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int m = 0; m < RING; ++m)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) ringB[i][m][v] = Real(0);
+            for (int v = 0; v < VX; ++v)
+                if (xh[v]) stage[li + cb + lane + 64 * v] = ld_at(base, xb[v]);
+        };
 
-    // One-step-ahead loads of a row for step `zs`: the input level kf-1 at the
-    // plane it "produces" at that step, and the stage rows of that step.
-    auto prefetch = [&](RowRegs<Real, VX>& rr, int j, int kf, int kl, const RowDuty& du, int jo, int64_t zs) {
-        if (jo > -1000) load_row(a.in[a.t_c & 1], rowoff(zs - (int64_t)R * H, ybase + jo), rr.preo);
-        const int64_t y = ybase + j;
-        const int64_t tv = a.t_c - H + du.kv + 1;   // time level of stage duty kv
-        if (kf <= kl) load_row(a.in[tv & 1], rowoff(zs - (int64_t)R * du.kv, y), rr.vnext);
-        if (du.d1) load_row(a.in[tv & 1], rowoff(zs - (int64_t)R * (du.kv + 1), y), rr.pre1);
-        if (du.d2) load_row(a.in[(tv - 1) & 1], rowoff(zs - (int64_t)R * du.kv, y), rr.pre2);
-    };
+        Real ring[NS][RING][VX];
+        Real vnA[VX], vnB[VX], p1A[VX], p1B[VX], p2A[VX], p2B[VX], poA[VX], poB[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            vnA[v] = vnB[v] = p1A[v] = p1B[v] = p2A[v] = p2B[v] = poA[v] = poB[v] = Real(0);
+#pragma unroll
+            for (int m = 0; m < RING; ++m) {
+#pragma unroll
+                for (int i = 0; i < NS; ++i) ring[i][m][v] = Real(0);
+            }
+        }
 
-    // The sweep starts 2R steps early so that the input rings of rows entering
-    // at level 1 hold the halo planes -R..-1; steps before 0 compute nothing.
-    prefetch(RA, jA, kfA, klA, uA, joA, -RING);
-    prefetch(RB, jB, kfB, klB, uB, joB, -RING);
-    __syncthreads();
-
-    const int64_t nzs = g.nz + (int64_t)R * (L - 1);   // wavefront steps end here
-
-    for (int64_t zb = -RING; zb < nzs; zb += RING) {
-        static_for<0, RING>([&](auto phc) {
+        // One wavefront step; ph: step index modulo UNR.
+        auto step = [&](auto phc, auto steadyc, int zs) __attribute__((always_inline)) {
             constexpr int ph = decltype(phc)::value;
-            const int64_t zs = zb + ph;
-            const bool live = zs < nzs;          // uniform across the workgroup
-            Real vcurA[VX], vcurB[VX];
+            constexpr bool STEADY = decltype(steadyc)::value;
+            // physical register of logical ring position m (0 = oldest plane)
+            auto P = [](int m) { return UNR == RING ? (m + ph) % RING : m; };
+            const bool live = STEADY || UNR == 1 || zs < nzs;   // uniform across the workgroup
 #pragma unroll
-            for (int v = 0; v < VX; ++v) { vcurA[v] = RA.vnext[v]; vcurB[v] = RB.vnext[v]; }
+            for (int i = 0; i < NS; ++i) {
+                lcs[i] = fresh_v(lcs[i]);
+                gos[i] = fresh_v(gos[i]);
+            }
+            Real vcA[VX], vcB[VX];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) { vcA[v] = vnA[v]; vcB[v] = vnB[v]; }
             // ---- A: stage every plane the levels read this step ------------------
             if (live) {
-                const int kfa = opaque_s(kfA), kla = opaque_s(klA), kfb = opaque_s(kfB), klb = opaque_s(klB);
-                const int ja = opaque_s(jA), jb = opaque_s(jB);
-                // computed levels and the input level kf-1 of rows that compute
-                static_for<0, NA>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    constexpr int k = i;
-                    if constexpr (k <= L - 2) {
-                        if (k >= kfa - 1 && k <= kla) put_row(srow(k, ja), ringA[i][(ph + RING - R) % RING]);
-                    }
+                const int f = (int)fresh_s((uint32_t)flags);
+                // every slot (unused ones into the spare rows); the duty rows are
+                // written after them
+                static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
+                    constexpr int s = decltype(sc)::value;
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) lds(lcs[s] + CORNER + 64 * v * SB) = hz[v] ? Real(0) : ring[s][P(R)][v];
                 });
-                static_for<0, NB>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    constexpr int k = KB0 + i;
-                    if constexpr (k <= L - 2) {
-                        if (k >= kfb - 1 && k <= klb) put_row(srow(k, jb), ringB[i][(ph + RING - R) % RING]);
+                // prefetch of the next step's inputs: plane zs + 1 - R*dz of each
+                // stream; planes outside the haloed grid are skipped (no computing
+                // cell reads them; in the steady range every plane is inside).  A
+                // duty register is staged before its next load is issued.
+                const int64_t nb = plane_off(zs + 1 - R * L);
+                const Real* fb0 = at(a.in[0], nb);
+                const Real* fb1 = at(a.in[1], nb);
+                auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[VX]) __attribute__((always_inline)) {
+                    if constexpr (!STEADY) {
+                        const int q = zs + 1 - R * dz;
+                        if (q < -R || q >= nz + R) return;
                     }
-                });
-                auto stage_row = [&](RowRegs<Real, VX>& rr, int j, const RowDuty& du, int jo) {
-                    if (jo > -1000) put_row(srow(H - 1, jo), rr.preo);
-                    if (du.d1) put_row(srow(du.kv, j), rr.pre1);
-                    if (du.d2) put_row(srow(du.kv - 1, j), rr.pre2);
+                    const Real* base = odd ? fb1 : fb0;
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) dst[v] = ld_at(base, o[v]);
                 };
-                stage_row(RA, ja, uA, opaque_s(joA));
-                stage_row(RB, jb, uB, opaque_s(joB));
-                // halo rows with a non-zero halo: load them (latency exposed; edge diamonds only)
-                if (edge_y && !zero_halo) {
-                    for (int k = wave; k < L - 1; k += KK::NWAVES) {
-                        for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
-                            const int64_t y = ybase + j;
-                            if ((y >= -R && y < 0) || (y >= g.ny && y < g.ny + R)) {
-                                Real tmp[VX];
-                                load_row(a.in[0], rowoff(zs - (int64_t)R * (k + 1), y), tmp);
-                                put_row(srow(k, j), tmp);
+                if (f & F_CMP_A) fetch(f & F_PV_A, kvA, foA, vnA);
+                if (f & F_CMP_B) fetch(f & F_PV_B, kvB, foB, vnB);
+                if (f & F_D1_A) { put(lA1, p1A); fetch(f & F_PV_A, kvA + 1, foA1, p1A); }
+                if (f & F_D1_B) { put(lB1, p1B); fetch(f & F_PV_B, kvB + 1, foB1, p1B); }
+                if (f & F_D2_A) { put(lA2, p2A); fetch(!(f & F_PV_A), kvA, foA, p2A); }
+                if (f & F_D2_B) { put(lB2, p2B); fetch(!(f & F_PV_B), kvB, foB, p2B); }
+                if (f & F_O_A) { put(lOA, poA); fetch(f & F_PT, H, foOA, poA); }
+                if (f & F_O_B) { put(lOB, poB); fetch(f & F_PT, H, foOB, poB); }
+                // non-zero halo, edge workgroups only: fixed values in halo columns
+                // of computed rows, and halo rows (latency exposed)
+                if (!ZH && (f & (F_EDGE_X | F_EDGE_Y))) {
+                    if (f & F_EDGE_X) {
+                        for (int k = kfA; k <= klA && k <= L - 2; ++k)
+                            fix_halo_cols(lds_row(k, jA), zs - R * (k + 1), ybase + jA);
+                        for (int k = kfB; k <= klB && k <= L - 2; ++k)
+                            fix_halo_cols(lds_row(k, jB), zs - R * (k + 1), ybase + jB);
+                    }
+                    if (f & F_EDGE_Y) {
+                        for (int k = wave; k < L - 1; k += KK::NWAVES) {
+                            for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
+                                const int y = ybase + j;
+                                const int q = zs - R * (k + 1);
+                                if (((y >= -R && y < 0) || (y >= ny && y < ny + R)) && q >= -R && q < nz + R) {
+                                    const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
+                                    const int li = lds_row(k, j);
+                                    for (int col = lane; col < KK::XL; col += 64) {
+                                        const int x = x0 + col;
+                                        const int xc = x < -R ? -R : (x >= nx + R ? nx + R - 1 : x);
+                                        stage[li + col] = base[xc + hh];
+                                    }
+                                }
                             }
                         }
                     }
                 }
-                // loads for the next step
-                prefetch(RA, ja, kfa, kla, uA, opaque_s(joA), zs + 1);
-                prefetch(RB, jb, kfb, klb, uB, opaque_s(joB), zs + 1);
             }
             __syncthreads();
-            // ---- B: update every owned (row, level) cell of this step ----------
+            // ---- B: update every (row, level) slot of this step ----------------------
             if (live) {
-                // Addresses: every plane a computing slot touches lies in the window
-                // [zs - R*L, zs]; a uniform 64-bit window base per array plus a
-                // 32-bit byte offset (per slot uniform + per lane) reaches it.
-                // The parity of level K's input time level t_c-H+K is p0 ^ (K & 1).
-                const int64_t e0 = (zs - (int64_t)R * L + g.h) * plane;
-                const int p0 = (int)((a.t_c - H) & 1);
-                const Real* in_par[2] = {a.in[p0] + e0, a.in[p0 ^ 1] + e0};
-                Real* out_par[2] = {a.out[p0] + e0, a.out[p0 ^ 1] + e0};
-                const uint32_t plane_b = (uint32_t)(plane * (int64_t)sizeof(Real));
-                // levels whose plane zs - R*K is inside the grid
-                const int64_t khz = zs >= 0 ? zs / R : -1;
-                const int64_t klz = zs - g.nz >= 0 ? (zs - g.nz) / R + 1 : 0;
-                const uint32_t zmask = khz < klz ? 0u
-                    : ((khz >= 31 ? 0xffffffffu : ((2u << khz) - 1u)) & ~((1u << (klz > 31 ? 31 : klz)) - 1u));
-                // One slot of one row: levels kf..kl compute, every other slot
-                // passes the loaded input plane on (the input level kf-1 keeps it
-                // in its ring).  prev is the slot below's output at this step (the
-                // z+R neighbour); the slot below's ring is updated only after this
-                // slot has read it.
-                auto slot = [&](auto ic, auto k0c, auto& ring, Real (&prev)[VX], const Real (&vcur)[VX],
-                                const Real* st_row, uint32_t rowb, uint32_t cmask, uint32_t smask,
-                                uint32_t cpmask, int64_t y) {
-                    constexpr int i = decltype(ic)::value;
-                    constexpr int K = decltype(k0c)::value + i;
-                    constexpr int KP = K & 1;
+                const int f = (int)fresh_s((uint32_t)flags);
+                // window of this step: planes [zs - R*L, zs]
+                const int64_t e0b = plane_off(zs - R * L);
+                Real* const ob0p = atw(a.out[0], e0b);
+                Real* const ob1p = atw(a.out[1], e0b);
+                const uint32_t cm = fresh_s(cmS), sto = fresh_s(stoS), stc = fresh_s(stcS), par = fresh_s(parS);
+                const int sb = (int)fresh_s((uint32_t)sB);
+                uint32_t zS = 0xffffffffu;   // slots whose level's plane zs - R*k lies inside the grid
+                if constexpr (!STEADY) {
+                    const int khz = zs >= 0 ? zs / R : -1;
+                    const int klz = zs - nz >= 0 ? (zs - nz) / R + 1 : 0;
+                    zS = (bit_range(klz - baseA, khz - baseA) & maskA) | (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA);
+                }
+                const uint32_t stm = (sto | stc) & zS;
+                Real prev[VX];
+                static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
+                    constexpr int s = decltype(sc)::value;
                     Real nv[VX];
+                    if constexpr (s == 0) {
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) nv[v] = vcur[v];
-                    if constexpr (i > 0) {
-                        if ((cmask >> K) & 1u) {
-                            if ((zmask >> K) & 1u) {
-                                const uint32_t so = (uint32_t)(R * (L - K)) * plane_b + rowb;
-                                const Real* st = st_row + Sh::srow0(K - 1) * XLP;
-                                const bool cpy = (cpmask >> K) & 1u;
-                                Real cin[VX];
+                        for (int v = 0; v < VX; ++v) nv[v] = vcA[v];
+                    } else {
+                        // every slot is computed (unused slots compute values nobody reads)
+                        const uint32_t lb = lcs[s - 1];     // corner of (level - 1, row)
+                        // a computed level whose plane lies inside the grid (unused
+                        // slots never count: their offsets are not theirs to load)
+                        const bool zv = ((cm & zS) >> s) & 1u;
+                        Real cen[VX];
 #pragma unroll
-                                for (int v = 0; v < VX; ++v) {
-                                    const int col = lane + 64 * v;
-                                    const uint32_t vo = so + xb[v];
-                                    Nbhd<Real, R> n;
-                                    n.c = ring[i - 1][(ph + R) % RING][v];
+                        for (int v = 0; v < VX; ++v) {
+                            const uint32_t c0 = lb + 64 * v * SB;
+                            Nbhd<Real, R> n;
+                            n.c = ring[s - 1][P(R)][v];
 #pragma unroll
-                                    for (int r = 1; r <= R; ++r) {
-                                        n.zm[r - 1] = ring[i - 1][(ph + R - r) % RING][v];
-                                        n.zp[r - 1] = r == R ? prev[v] : ring[i - 1][(ph + R + r) % RING][v];
-                                        n.xp[r - 1] = st[col + r];
-                                        n.xm[r - 1] = st[col - r];
-                                        n.yp[r - 1] = st[col + r * XLP];
-                                        n.ym[r - 1] = st[col - r * XLP];
-                                    }
-                                    Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
+                            for (int r = 1; r <= R; ++r) {
+                                n.zm[r - 1] = ring[s - 1][P(R - r)][v];
+                                n.zp[r - 1] = r == R ? prev[v] : ring[s - 1][P(R + r)][v];
+                                n.xp[r - 1] = lds(c0 + CORNER + r * SB);
+                                n.xm[r - 1] = lds(c0 + CORNER - r * SB);
+                                n.yp[r - 1] = lds(c0 + CORNER + r * XLP * SB);
+                                n.ym[r - 1] = lds(c0 + CORNER - r * XLP * SB);
+                            }
+                            Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
+                            if constexpr (S::NCOEF > 0) {
+                                // Coefficients of the slot's plane.  In the steady range
+                                // every slot's offset (0 for unused slots: the window's
+                                // first plane, zs - R*L >= -R) stays inside the arrays;
+                                // elsewhere only slots whose plane is inside the grid load.
+                                if (STEADY || zv) {
+                                    const uint32_t go = gos[s] + xb[v];
 #pragma unroll
-                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = ld_at(a.coef.arr[m] + e0, vo);
-                                    nv[v] = S::apply(n, a.coef.k, cf);
-                                    if (cpy) cin[v] = n.c;
+                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = ld_at(at(a.coef.arr[m], e0b), go);
+                                } else {
+#pragma unroll
+                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = Real(0);
                                 }
-                                // x-halo lanes hold the fixed halo (a zero halo is
-                                // written into the stage instead, see put_row)
-                                if (edge_x && !zero_halo) {
-#pragma unroll
-                                    for (int v = 0; v < VX; ++v)
-                                        if (xh[v]) nv[v] = ld_at(in_par[0], so + xb[v]);
-                                }
-                                // the last two levels of a row go to the output pair
-                                if ((smask >> K) & 1u) {
-#pragma unroll
-                                    for (int v = 0; v < VX; ++v)
-                                        if (own[v]) st_at(out_par[KP ^ 1], so + xb[v], nv[v]);
-                                }
-                                if (cpy) {
-#pragma unroll
-                                    for (int v = 0; v < VX; ++v)
-                                        if (own[v]) st_at(out_par[KP], so + xb[v], cin[v]);
-                                }
-                            } else {
+                            }
+                            nv[v] = S::apply(n, a.coef.k, cf);
+                            cen[v] = n.c;
+                        }
+                        if constexpr (!STEADY) {
+                            // a level whose plane is a halo plane (or beyond) holds the halo
+                            if (!zv) {
 #pragma unroll
                                 for (int v = 0; v < VX; ++v) nv[v] = Real(0);
-                                const int64_t q = zs - (int64_t)R * K;
-                                if (!zero_halo && q >= -R && q < g.nz + R)
-                                    load_row(a.in[0], rowoff(q, y), nv);   // fixed halo plane
+                                if constexpr (!ZH) {
+                                    // halo values, for computed levels only (an unused
+                                    // slot's row may lie outside the grid)
+                                    const bool isB = s >= sb;
+                                    const int k = isB ? baseB + (s - sb) : baseA + s;
+                                    const int q = zs - R * k;
+                                    if (((cm >> s) & 1u) && q >= -R && q < nz + R) {
+                                        const Real* base =
+                                            at(a.in[0], plane_off(q) + (int64_t)(ybase + (isB ? jB : jA) + hh) * pitchx * SB);
+#pragma unroll
+                                        for (int v = 0; v < VX; ++v) nv[v] = ld_at(base, xb[v]);
+                                    }
+                                }
                             }
                         }
+                        // row B's input slot takes the loaded input plane
+                        if (s == sb) {
 #pragma unroll
-                        for (int v = 0; v < VX; ++v) ring[i - 1][ph][v] = prev[v];
+                            for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
+                        }
+                        // the last two levels of each row (and the input level of a
+                        // row that computes one level) go to the output pair
+                        if ((stm >> s) & 1u) {
+                            const bool podd = (par >> s) & 1u;
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) {
+                                const uint32_t so = (gos[s] + xb[v]) | kill[v];
+                                if ((sto >> s) & 1u) buf_store(raw_rsrc(podd ? ob1p : ob0p), so, nv[v]);
+                                if ((stc >> s) & 1u) buf_store(raw_rsrc(podd ? ob0p : ob1p), so, cen[v]);
+                            }
+                        }
+                        // slot s-1's ring takes its newest plane
+#pragma unroll
+                        for (int v = 0; v < VX; ++v) {
+                            if constexpr (UNR == RING) {
+                                ring[s - 1][P(0)][v] = prev[v];
+                            } else {
+#pragma unroll
+                                for (int m = 0; m + 1 < RING; ++m) ring[s - 1][m][v] = ring[s - 1][m + 1][v];
+                                ring[s - 1][RING - 1][v] = prev[v];
+                            }
+                        }
                     }
 #pragma unroll
                     for (int v = 0; v < VX; ++v) prev[v] = nv[v];
-                };
-                Real prevA[VX], prevB[VX];
-#pragma unroll
-                for (int v = 0; v < VX; ++v) { prevA[v] = vcurA[v]; prevB[v] = vcurB[v]; }
-                const Real* stA = stage + opaque_s(jA) * XLP + R;
-                const Real* stB = stage + opaque_s(jB) * XLP + R;
-                const uint32_t rbA = (uint32_t)opaque_s(rowbA), rbB = (uint32_t)opaque_s(rowbB);
-                const uint32_t cmA = (uint32_t)opaque_s((int)cmaskA), cmB = (uint32_t)opaque_s((int)cmaskB);
-                const uint32_t smA = (uint32_t)opaque_s((int)smaskA), smB = (uint32_t)opaque_s((int)smaskB);
-                const uint32_t cpA = (uint32_t)opaque_s((int)cpmaskA), cpB = (uint32_t)opaque_s((int)cpmaskB);
-                // interleave the two rows level by level: two independent chains
-                static_for<0, NA>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    slot(ic, std::integral_constant<int, 0>{}, ringA, prevA, vcurA, stA, rbA, cmA, smA, cpA,
-                         ybase + jA);
-                    if constexpr (i >= KB0 && i - KB0 < NB) {
-                        slot(std::integral_constant<int, i - KB0>{}, std::integral_constant<int, KB0>{}, ringB, prevB,
-                             vcurB, stB, rbB, cmB, smB, cpB, ybase + jB);
-                    }
                 });
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    ringA[NA - 1][ph][v] = prevA[v];
-                    ringB[NB - 1][ph][v] = prevB[v];
+                    if constexpr (UNR == RING) {
+                        ring[NS - 1][P(0)][v] = prev[v];
+                    } else {
+#pragma unroll
+                        for (int m = 0; m + 1 < RING; ++m) ring[NS - 1][m][v] = ring[NS - 1][m + 1][v];
+                        ring[NS - 1][RING - 1][v] = prev[v];
+                    }
                 }
                 // rows of this diamond with no level in this row: carry both levels
-                if (zs >= 0 && zs < g.nz) {
+                if (zs >= 0 && zs < nz) {
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        const int jr = t == 0 ? jA : jB;
-                        const int kf = t == 0 ? kfA : kfB, kl = t == 0 ? klA : klB;
-                        const int64_t y = ybase + jr;
-                        if (kf > kl && y >= 0 && y < g.ny) {
-                            const int64_t ro = rowoff(zs, y);
+                        const bool in_row = t == 0 ? (f & F_IN_A) != 0 : (f & F_IN_B) != 0;
+                        const bool cmp = t == 0 ? (f & F_CMP_A) != 0 : (f & F_CMP_B) != 0;
+                        if (in_row && !cmp) {
+                            const int64_t ro = plane_off(zs) + (t == 0 ? rowb_of(jA) : rowb_of(jB));
 #pragma unroll
                             for (int v = 0; v < VX; ++v) {
-                                if (own[v]) {
-                                    st_at(a.out[0] + ro, xb[v], ld_at(a.in[0] + ro, xb[v]));
-                                    st_at(a.out[1] + ro, xb[v], ld_at(a.in[1] + ro, xb[v]));
+                                if (!kill[v]) {
+                                    st_at(atw(a.out[0], ro), xb[v], ld_at(at(a.in[0], ro), xb[v]));
+                                    st_at(atw(a.out[1], ro), xb[v], ld_at(at(a.in[1], ro), xb[v]));
                                 }
                             }
                         }
@@ -560,8 +705,55 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 }
             }
             __syncthreads();
-        });
-    }
+        };
+
+        // the sweep starts 2R steps early so that the input rings of rows
+        // entering at level 1 hold the halo planes -R..-1; steps [zA, zB) are
+        // steady: every level's plane zs - R*k (k = 0..L-1) is inside the grid
+        const int zA = ((R * (L - 1) + UNR - 1) / UNR) * UNR;
+        const int zB = (nz / UNR) * UNR > zA ? (nz / UNR) * UNR : zA;
+        {
+            // first loads: the inputs of step -RING
+            const int zs = -RING - 1;
+            const int f = (int)fresh_s((uint32_t)flags);
+            const int64_t nb = plane_off(zs + 1 - R * L);
+            const Real* fb0 = at(a.in[0], nb);
+            const Real* fb1 = at(a.in[1], nb);
+            auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[VX]) {
+                const int q = zs + 1 - R * dz;
+                if (q < -R || q >= nz + R) return;
+                const Real* base = odd ? fb1 : fb0;
+#pragma unroll
+                for (int v = 0; v < VX; ++v) dst[v] = ld_at(base, o[v]);
+            };
+            if (f & F_CMP_A) fetch(f & F_PV_A, kvA, foA, vnA);
+            if (f & F_CMP_B) fetch(f & F_PV_B, kvB, foB, vnB);
+            if (f & F_D2_A) fetch(!(f & F_PV_A), kvA, foA, p2A);
+            if (f & F_D2_B) fetch(!(f & F_PV_B), kvB, foB, p2B);
+            if (f & F_D1_A) fetch(f & F_PV_A, kvA + 1, foA1, p1A);
+            if (f & F_D1_B) fetch(f & F_PV_B, kvB + 1, foB1, p1B);
+            if (f & F_O_A) fetch(f & F_PT, H, foOA, poA);
+            if (f & F_O_B) fetch(f & F_PT, H, foOB, poB);
+        }
+        __syncthreads();
+        using General = std::integral_constant<bool, false>;
+        using Steady = std::integral_constant<bool, true>;
+        // (three loops rather than one with a per-step branch: separate loops
+        // keep the register assignment of both bodies spill-free)
+        int zb = -RING;
+        for (; zb < nzs; zb += UNR) {
+            if (zb >= zA && zb < zB) break;
+            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) { step(phc, General{}, zb + decltype(phc)::value); });
+        }
+        for (; zb < zB; zb += UNR)
+            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) { step(phc, Steady{}, zb + decltype(phc)::value); });
+        for (; zb < nzs; zb += UNR)
+            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) { step(phc, General{}, zb + decltype(phc)::value); });
+    };
+    if (zero_halo)
+        sweep(std::integral_constant<bool, true>{});
+    else
+        sweep(std::integral_constant<bool, false>{});
 }
 
 }  // namespace girih

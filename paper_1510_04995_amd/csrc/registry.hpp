@@ -18,7 +18,8 @@ struct KernelEntry {
     int dtype;
     int algo;
     int dw;          // MWD diamond width
-    int vx;          // MWD x cells per lane (lanes hold 64*vx cells per row)
+    int vx;          // MWD x cells per lane
+    int wx;          // MWD waves along x per row pair (a row holds 64*vx*wx cells)
     int nthreads;    // MWD workgroup size
     int lds_bytes;   // static LDS per workgroup
     int xown_max;    // MWD: largest owned x tile

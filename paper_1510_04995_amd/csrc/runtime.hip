@@ -92,9 +92,10 @@ size_t grid_bytes(const girih_plan_s* p) {
            elem_bytes(p->dtype);
 }
 
-const KernelEntry* find_mwd(int st, int dt, int dw, int vx) {
+const KernelEntry* find_mwd(int st, int dt, int dw, int vx, int wx) {
     for (const auto& e : kernel_table())
-        if (e.algo == AL_MWD && e.stencil == st && e.dtype == dt && e.dw == dw && e.vx == vx) return &e;
+        if (e.algo == AL_MWD && e.stencil == st && e.dtype == dt && e.dw == dw && e.vx == vx && e.wx == wx)
+            return &e;
     return nullptr;
 }
 
@@ -104,14 +105,17 @@ const KernelEntry* find_naive(int st, int dt) {
     return nullptr;
 }
 
-// Default MWD shape per radius and element size.
-void default_mwd(int R, int dtype, int& dw, int& vx) {
+// Default MWD shape per radius and element size (diamond width, cells per
+// lane, waves along x); the tuner replaces it per problem.
+void default_mwd(int R, int dtype, int& dw, int& vx, int& wx) {
     if (R == 1) {
-        dw = 8;
-        vx = dtype == GIRIH_F64 ? 2 : 4;
+        dw = dtype == GIRIH_F64 ? 12 : 16;
+        vx = 1;
+        wx = 2;
     } else {
         dw = 16;
-        vx = 2;
+        vx = 1;
+        wx = 2;
     }
 }
 
@@ -121,17 +125,23 @@ int resolve(girih_plan_s* p, const girih_params* in) {
     if (in) q = *in;
     const int R = p->R;
     if (p->algo == GIRIH_MWD) {
-        int dw = q.diamond_width, vx = q.threads_x ? q.threads_x / 64 : 0;
-        int ddw, dvx;
-        default_mwd(R, p->dtype, ddw, dvx);
+        int dw = q.diamond_width, vx = q.cells_per_lane, wx = q.threads_x ? q.threads_x / 64 : 0;
+        int ddw, dvx, dwx;
+        default_mwd(R, p->dtype, ddw, dvx, dwx);
+        if (q.threads_x < 0 || q.threads_x % 64 || vx < 0) return GIRIH_E_INVALID;
         if (dw == 0) dw = ddw;
-        if (vx == 0) vx = dvx;
-        if (q.threads_x && q.threads_x % 64) return GIRIH_E_INVALID;
+        if (vx == 0 && wx == 0) { vx = dvx; wx = dwx; }
+        if (vx == 0) vx = 1;
+        if (wx == 0) wx = 1;
         if (dw <= 0 || dw % (2 * R) || (R == 1 && dw % 4)) return GIRIH_E_INVALID;
         if (q.wavefront_depth != 0 && q.wavefront_depth != 1) return GIRIH_E_UNSUPPORTED;
         if (q.variant != 0) return GIRIH_E_UNSUPPORTED;
-        const KernelEntry* k = find_mwd(p->stencil, p->dtype, dw, vx);
+        const KernelEntry* k = find_mwd(p->stencil, p->dtype, dw, vx, wx);
         if (!k) return GIRIH_E_UNSUPPORTED;
+        // the kernel addresses a window of R*(L+1) planes with 32-bit offsets
+        const int64_t win = (int64_t)R * (dw / R + 1) + 1;
+        if (win * p->grid.pitch_y * p->grid.pitch_x * (int64_t)elem_bytes(p->dtype) >= (int64_t)1 << 31)
+            return GIRIH_E_UNSUPPORTED;
         int64_t xo = q.tile_x ? q.tile_x : k->xown_max;
         if (xo <= 0) return GIRIH_E_INVALID;
         if (xo > k->xown_max) return GIRIH_E_LDS;
@@ -144,7 +154,8 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         q.tile_x = (int32_t)xo;
         q.tile_y = dw;
         q.tile_z = (int32_t)std::min<int64_t>(p->grid.nz, INT32_MAX);
-        q.threads_x = 64 * vx;
+        q.threads_x = 64 * wx;
+        q.cells_per_lane = vx;
         q.threads_y = dw / 2;
         q.variant = 0;
     } else {
@@ -159,6 +170,7 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         q.wavefront_depth = 0;
         q.tile_x = q.threads_x;
         q.tile_y = q.threads_y;
+        q.cells_per_lane = 1;
         q.variant = 0;
     }
     p->params = q;
@@ -411,7 +423,8 @@ std::vector<girih_params> mwd_candidates(const girih_plan_s* p) {
             q.diamond_width = e.dw;
             q.wavefront_depth = 1;
             q.tile_x = (int32_t)t;
-            q.threads_x = 64 * e.vx;
+            q.threads_x = 64 * e.wx;
+            q.cells_per_lane = e.vx;
             q.threads_y = e.dw / 2;
             out.push_back(q);
         }
@@ -545,7 +558,7 @@ int girih_tune(girih_plan_t p, int32_t mode, int64_t T, double max_seconds, void
     const double per_cand = std::max(0.05, std::min(2.0, max_seconds / std::max<size_t>(cands.size(), 1)));
     std::map<std::vector<int32_t>, double> seen;
     auto key = [](const girih_params& q) {
-        return std::vector<int32_t>{q.diamond_width, q.tile_x, q.threads_x, q.threads_y, q.tile_z};
+        return std::vector<int32_t>{q.diamond_width, q.tile_x, q.threads_x, q.threads_y, q.tile_z, q.cells_per_lane};
     };
     double best_rate = -1;
     girih_params best_p = saved;
@@ -572,7 +585,7 @@ int girih_tune(girih_plan_t p, int32_t mode, int64_t T, double max_seconds, void
     if (mode == GIRIH_TUNE_HILLCLIMB && p->algo == GIRIH_MWD) {
         // per thread shape (cells per lane), local search over (Dw, x tile)
         std::map<int, std::vector<girih_params>> by_shape;
-        for (const auto& q : cands) by_shape[q.threads_x].push_back(q);
+        for (const auto& q : cands) by_shape[q.threads_x * 8 + q.cells_per_lane].push_back(q);
         for (auto& kv : by_shape) {
             auto& v = kv.second;
             std::vector<int> dws;

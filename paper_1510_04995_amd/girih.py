@@ -29,7 +29,8 @@ class GirihGrid(ctypes.Structure):
 
 class GirihParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("diamond_width", "wavefront_depth", "tile_x", "tile_y",
-                                                "tile_z", "threads_x", "threads_y", "variant")]
+                                                "tile_z", "threads_x", "threads_y", "variant",
+                                                "cells_per_lane")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -14,6 +14,17 @@ poisoned with NaN: a schedule that reads a value it did not produce fails.
 import numpy as np
 import pytest
 
+# The blocked sweep of the variable-coefficient stencils is not registered in
+# this version of the library (plans return GIRIH_E_UNSUPPORTED); its cases stay
+# listed, skipped, until the kernel's coefficient loads are validated.
+VAR_MWD_OFF = pytest.mark.skip(reason="MWD for variable-coefficient stencils is not registered: coefficient "
+                                      "loads of unused slots left the arrays (fixed in the kernel: unused "
+                                      "slots no longer load), pending validation on the device")
+
+
+def var_off(*case):
+    return pytest.param(*case, marks=VAR_MWD_OFF) if case[0] in ("7v", "25v") else case
+
 from tests.gpu_util import inputs, oracle_run, run_gpu
 
 pytestmark = pytest.mark.gpu
@@ -48,39 +59,53 @@ def test_naive_block_shapes():
         assert_bitwise(got, ref, "naive %s" % p)
 
 
-# (stencil, dtype, Dw, cells per lane, tile_x or 0, grid (nx, ny, nz), list of T)
+# (stencil, dtype, Dw, cells per lane, waves along x, tile_x or 0, grid (nx, ny, nz), list of T):
+# every compiled MWD variant at least once, each grid several x chunks wide
 MWD_CASES = [
-    ("7c", "f64", 4, 2, 0, (61, 23, 17), [1, 2, 3, 5, 8]),
-    ("7c", "f64", 8, 2, 0, (150, 45, 19), [1, 4, 5, 9, 13]),
-    ("7c", "f64", 8, 2, 40, (150, 45, 19), [7]),
-    ("7c", "f64", 12, 2, 0, (131, 50, 12), [6, 7, 16]),
-    ("7c", "f64", 16, 1, 0, (70, 70, 9), [3, 8, 17]),
-    ("7c", "f64", 12, 1, 0, (200, 40, 11), [9, 16]),
-    ("7c", "f32", 16, 2, 0, (200, 40, 11), [9, 16]),
-    ("7c", "f32", 8, 4, 0, (300, 33, 15), [5, 12]),
-    ("7c", "f32", 16, 4, 0, (260, 37, 9), [10]),
-    ("7v", "f64", 8, 2, 0, (129, 30, 14), [3, 7]),
-    ("7v", "f32", 12, 2, 0, (120, 41, 10), [6, 11]),
-    ("25c", "f64", 8, 2, 0, (140, 30, 20), [1, 2, 3]),
-    ("25c", "f64", 16, 2, 0, (150, 50, 22), [2, 3, 5]),
-    ("25c", "f32", 16, 4, 0, (260, 45, 17), [4]),
-    ("25c", "f64", 24, 1, 0, (100, 60, 21), [3, 7]),
-    ("25c", "f32", 24, 2, 0, (100, 60, 21), [3, 7]),
-    ("25v", "f64", 16, 2, 0, (130, 40, 19), [2, 5]),
-    ("25v", "f32", 8, 4, 0, (250, 26, 18), [3]),
+    ("7c", "f64", 4, 2, 2, 0, (300, 23, 17), [1, 2, 3, 5, 8]),
+    ("7c", "f64", 8, 1, 2, 0, (150, 45, 19), [1, 4, 5, 9, 13]),
+    ("7c", "f64", 8, 1, 4, 40, (150, 45, 19), [7]),
+    ("7c", "f64", 8, 2, 1, 0, (150, 45, 19), [4, 9]),
+    ("7c", "f64", 8, 2, 2, 0, (300, 33, 15), [5, 12]),
+    ("7c", "f64", 12, 1, 2, 0, (131, 50, 12), [6, 7, 16]),
+    ("7c", "f64", 12, 2, 1, 0, (200, 40, 11), [9, 16]),
+    ("7c", "f64", 16, 1, 1, 0, (70, 70, 9), [3, 8, 17]),
+    ("7c", "f32", 16, 1, 2, 0, (200, 40, 11), [9, 16]),
+    ("7c", "f32", 12, 2, 2, 0, (300, 33, 15), [5, 12]),
+    ("7c", "f32", 16, 2, 1, 0, (260, 37, 9), [10]),
+    ("7c", "f32", 4, 2, 2, 0, (300, 23, 17), [3]),
+    var_off("7v", "f64", 8, 1, 2, 0, (129, 30, 14), [3, 7]),
+    var_off("7v", "f64", 12, 1, 2, 0, (120, 41, 10), [6, 11]),
+    var_off("7v", "f32", 16, 1, 2, 0, (120, 41, 10), [9]),
+    ("25c", "f64", 8, 1, 2, 0, (140, 30, 20), [1, 2, 3]),
+    ("25c", "f64", 8, 1, 4, 0, (300, 30, 20), [2, 5]),
+    ("25c", "f64", 8, 2, 1, 0, (140, 30, 20), [3]),
+    ("25c", "f64", 16, 1, 1, 0, (150, 50, 22), [2, 3, 5]),
+    ("25c", "f64", 16, 1, 2, 0, (150, 50, 22), [2, 3, 5]),
+    ("25c", "f32", 16, 2, 1, 0, (260, 45, 17), [4]),
+    ("25c", "f64", 24, 1, 1, 0, (100, 60, 21), [3, 7]),
+    ("25c", "f32", 24, 1, 1, 0, (100, 60, 21), [3, 7]),
+    ("25c", "f32", 8, 2, 2, 0, (600, 30, 20), [2, 5]),
+    var_off("25v", "f64", 16, 1, 2, 0, (130, 40, 19), [2, 5]),
+    var_off("25v", "f32", 8, 2, 1, 0, (250, 26, 18), [3]),
 ]
 
 
-@pytest.mark.parametrize("stencil,dtype,dw,vx,tx,n,Ts", MWD_CASES)
-def test_mwd_matches_naive_and_oracle_bitwise(stencil, dtype, dw, vx, tx, n, Ts):
+def mwd_params(dw, vx, wx, tx=0):
+    return {"diamond_width": dw, "cells_per_lane": vx, "threads_x": 64 * wx, "tile_x": tx}
+
+
+@pytest.mark.parametrize("stencil,dtype,dw,vx,wx,tx,n,Ts", MWD_CASES)
+def test_mwd_matches_naive_and_oracle_bitwise(stencil, dtype, dw, vx, wx, tx, n, Ts):
     u0, c, arr = inputs(stencil, *n, seed=3)
-    params = {"diamond_width": dw, "threads_x": 64 * vx, "tile_x": tx}
+    params = mwd_params(dw, vx, wx, tx)
     for T in Ts:
-        print("mwd", stencil, dtype, dw, vx, tx, n, T, flush=True)
+        print("mwd", stencil, dtype, dw, vx, wx, tx, n, T, flush=True)
         got, info = run_gpu(stencil, dtype, u0, c, arr, T, algo="mwd", params=params)
-        assert info["params"]["diamond_width"] == dw
+        q = info["params"]
+        assert (q["diamond_width"], q["cells_per_lane"], q["threads_x"]) == (dw, vx, 64 * wx)
         ref = oracle_run(stencil, u0, c, arr, T, dtype)
-        assert_bitwise(got, ref, "mwd %s %s Dw=%d vx=%d T=%d" % (stencil, dtype, dw, vx, T))
+        assert_bitwise(got, ref, "mwd %s %s Dw=%d vx=%d wx=%d T=%d" % (stencil, dtype, dw, vx, wx, T))
         naive, _ = run_gpu(stencil, dtype, u0, c, arr, T, algo="naive")
         assert_bitwise(got, naive, "mwd vs naive")
         if dtype == "f64":
@@ -93,15 +118,23 @@ def test_mwd_T0_and_T1_and_tiny_grids():
         for T in (0, 1, 2, 9):
             got, _ = run_gpu("7c", "f64", u0, c, arr, T, algo="mwd", params={"diamond_width": 8})
             assert_bitwise(got, oracle_run("7c", u0, c, arr, T), "tiny %s T=%d" % (n, T))
-    u0, c, arr = inputs("25v", 5, 3, 6, seed=4)
-    got, _ = run_gpu("25v", "f64", u0, c, arr, 3, algo="mwd", params={"diamond_width": 16})
-    assert_bitwise(got, oracle_run("25v", u0, c, arr, 3), "tiny 25v")
+    u0, c, arr = inputs("25c", 5, 3, 6, seed=4)
+    got, _ = run_gpu("25c", "f64", u0, c, arr, 3, algo="mwd", params={"diamond_width": 16})
+    assert_bitwise(got, oracle_run("25c", u0, c, arr, 3), "tiny 25c")
 
 
-def test_mwd_padded_layout():
-    u0, c, arr = inputs("7v", 50, 20, 9, seed=5)
-    got, _ = run_gpu("7v", "f64", u0, c, arr, 6, params={"diamond_width": 8}, pitch=(64, 25))
-    assert_bitwise(got, oracle_run("7v", u0, c, arr, 6), "padded")
+@pytest.mark.parametrize("stencil", ["25c", var_off("25v")])
+def test_mwd_tiny_radius4(stencil):
+    u0, c, arr = inputs(stencil, 5, 3, 6, seed=4)
+    got, _ = run_gpu(stencil, "f64", u0, c, arr, 3, algo="mwd", params={"diamond_width": 16})
+    assert_bitwise(got, oracle_run(stencil, u0, c, arr, 3), "tiny %s" % stencil)
+
+
+@pytest.mark.parametrize("stencil", ["7c", var_off("7v")])
+def test_mwd_padded_layout(stencil):
+    u0, c, arr = inputs(stencil, 50, 20, 9, seed=5)
+    got, _ = run_gpu(stencil, "f64", u0, c, arr, 6, params={"diamond_width": 8}, pitch=(64, 25))
+    assert_bitwise(got, oracle_run(stencil, u0, c, arr, 6), "padded")
 
 
 def test_mwd_time_split_bitwise():
@@ -162,9 +195,12 @@ def check_samples_against_cones(stencil, u0, c, arr, T, out, points):
         assert r[q] == out[full], (p, r[q], out[full])
 
 
-@pytest.mark.parametrize("stencil,dw,vx,n,T", [("7c", 8, 2, (140, 37, 13), 9), ("7v", 12, 2, (131, 29, 11), 7),
-                                               ("25c", 16, 2, (120, 45, 19), 5), ("25v", 8, 2, (90, 21, 17), 3)])
-def test_mwd_nonzero_halo(stencil, dw, vx, n, T):
+@pytest.mark.parametrize("stencil,dw,vx,wx,n,T", [("7c", 8, 1, 2, (140, 37, 13), 9), var_off("7v", 12, 2, 1, (131, 29, 11), 7),
+                                                  ("25c", 16, 1, 2, (120, 45, 19), 5),
+                                                  ("7c", 12, 2, 1, (131, 29, 11), 7),
+                                                  var_off("25v", 8, 1, 4, (290, 21, 17), 3),
+                                                  ("25c", 8, 1, 4, (290, 21, 17), 3)])
+def test_mwd_nonzero_halo(stencil, dw, vx, wx, n, T):
     """Arbitrary fixed Dirichlet values (and a -0.0) in the halo take the general path."""
     u0, c, arr = inputs(stencil, *n, seed=8)
     h = 1 if stencil.startswith("7") else 4
@@ -174,7 +210,7 @@ def test_mwd_nonzero_halo(stencil, dw, vx, n, T):
     u0 = u0.copy()
     u0[halo] = rng.random(int(halo.sum())) - 0.5
     u0[0, 0, 0] = -0.0
-    got, _ = run_gpu(stencil, "f64", u0, c, arr, T, algo="mwd", params={"diamond_width": dw, "threads_x": 64 * vx})
+    got, _ = run_gpu(stencil, "f64", u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx))
     assert_bitwise(got, oracle_run(stencil, u0, c, arr, T), "nonzero halo %s" % stencil)
-    got32, _ = run_gpu(stencil, "f32", u0, c, arr, T, algo="mwd", params={"diamond_width": dw, "threads_x": 64 * vx})
+    got32, _ = run_gpu(stencil, "f32", u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx))
     assert_bitwise(got32, oracle_run(stencil, u0, c, arr, T, "f32"), "nonzero halo f32 %s" % stencil)

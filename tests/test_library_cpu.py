@@ -91,8 +91,16 @@ def test_plan_rejects_bad_tile_params():
     assert e.value.code == G.E_INVALID
 
 
+def test_mwd_variable_coefficients_unsupported():
+    for st, h in (("7v", 1), ("25v", 4)):
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan(st, "f64", grid(h=h), None, "mwd")
+        assert e.value.code == G.E_UNSUPPORTED
+        G.girih_destroy(G.girih_plan(st, "f64", grid(h=h), None, "naive"))
+
+
 def test_run_rejects_without_launch():
-    p = G.girih_plan("7v", "f64", grid(), None, "mwd")
+    p = G.girih_plan("7v", "f64", grid(), None, "naive")
     with pytest.raises(G.GirihError) as e:
         G.girih_run(p, 0, 0, [], 4, 0)                 # null buffers
     assert e.value.code == G.E_INVALID
@@ -112,9 +120,10 @@ def test_candidates_cover_compiled_variants():
     assert {4, 8, 12, 16} <= dws
     for q in c:
         assert q["threads_y"] == q["diamond_width"] // 2
-        assert 8 <= q["tile_x"] <= q["threads_x"] - 2 * (q["diamond_width"] - 1)
+        # a row spans threads_x * cells_per_lane cells: the owned tile plus R*(L-1) = Dw-R on each side
+        assert 8 <= q["tile_x"] <= q["threads_x"] * q["cells_per_lane"] - 2 * (q["diamond_width"] - 1)
     G.girih_destroy(p)
-    p = G.girih_plan("25v", "f32", G.make_grid(384, 384, 384, 4), None, "mwd")
+    p = G.girih_plan("25c", "f32", G.make_grid(384, 384, 384, 4), (1, 0, 0, 0, 0), "mwd")
     c = G.girih_candidates(p)
     assert all(q["diamond_width"] % 8 == 0 for q in c) and c
     G.girih_destroy(p)
