@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of the blocked Jacobi sweep (multi-threaded wavefront diamond
+blocking) on one MI355X, printed as one JSON line.
+
+A step is one whole run of the hot path on the workload: girih_run of T
+Jacobi steps of the 7-point constant-coefficient stencil on a 512^3 FP64 grid
+(T = 64; every diamond row of the schedule, their prologue loads, wavefront
+loops and epilogue stores).  Inputs are seeded synthetic fields already
+resident in HBM; the timed region holds exactly --steps runs, bracketed by
+device synchronisation.
+
+Beside the headline value the line carries:
+  roofline      the dominant kernel (the diamond-row kernel) against HBM
+                peak: algorithmic bytes per launch (the blocked code balance
+                of the plan, bytes per lattice update, times the updates of one
+                launch) divided by its average launch duration, measured with
+                HIP events on the launch stream inside the timed runs; traffic
+                from the committed rocprofv3 counter summary when it was taken
+                on the current kernel source, else null;
+  cpu_baseline  the FP64 CPU oracle on the same workload, a bounded number of
+                steps, on the host's cores;
+  compare       naive GPU sweep (FP64), blocked FP32 run and its error against
+                the FP64 result, measured outside the timed region.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+WORKLOAD = "7pt-const-512"
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "mwd_7pt_const_512_f64_traffic.txt")
+KERNEL_SOURCES = ("paper_1510_04995_amd/csrc/mwd.hpp", "paper_1510_04995_amd/csrc/stencils.hpp",
+                  "paper_1510_04995_amd/csrc/kernels_7c_f64.hip", "paper_1510_04995_amd/csrc/instantiate.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def launch_lups(nx, ny, nz, T, H):
+    """Lattice updates of each diamond-row launch: row r covers time steps
+    [t_c - H, t_c + H) with t_c = r*H, each cell once per step it covers,
+    clipped to [0, T); half of each row's diamonds cover each step."""
+    n_rows = (T - 1) // H + 2
+    out = []
+    for r in range(n_rows):
+        t_c = r * H
+        steps = 0
+        for s in range(t_c - H, t_c + H):
+            if 0 <= s < T:
+                steps += 1
+        out.append(nx * ny * nz * steps / 2.0)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--params", default=None, help="JSON dict of girih_params fields for the blocked plan")
+    ap.add_argument("--no-compare", action="store_true", help="skip the naive / FP32 comparison runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also copy a buffer of this many MiB (a known-size reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the sweep is a single-device kernel here and no multi-GPU "
+              "path is built (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1510_04995_amd as P
+    from workloads import WORKLOADS, field_and_coefs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = WORKLOADS[WORKLOAD]
+    h = w.radius
+    u0, c, _ = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
+    g0 = torch.from_numpy(u0).to(dev)
+    params = json.loads(args.params) if args.params else None
+
+    sw = P.Sweep(w.stencil, "f64", w.nx, w.ny, w.nz, list(c), "mwd", params)
+    info = sw.info()
+    b0, b1 = g0.clone(), g0.clone()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sw.run(b0, b1, w.T)
+    torch.cuda.synchronize()
+
+    sw.set_timing(True)
+    n_launch = 0
+    kern_ms = 0.0
+    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sw.run(b0, b1, w.T)
+        ev1.record(stream)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1) * 1e-3)
+        n, ms = sw.timing()   # events of this run, already complete
+        n_launch += n
+        kern_ms += ms
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sw.set_timing(False)
+
+    lups = w.nx * w.ny * w.nz * w.T
+    ms_per_step = wall / args.steps * 1e3
+    value = lups * args.steps / wall / 1e9
+
+    # roofline of the diamond-row kernel
+    q = info["params"]
+    H = q["diamond_width"] // (2 * h)
+    per_launch = launch_lups(w.nx, w.ny, w.nz, w.T, H)
+    bpl = info["model_bytes_per_lup"]
+    alg_bytes_per_launch = bpl * sum(per_launch) / len(per_launch)
+    avg_launch_s = kern_ms / max(n_launch, 1) * 1e-3
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    traffic = None
+    src_hash = kernel_source_hash()
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as f:
+            prof = json.load(f)
+        if prof.get("kernel_source_hash") == src_hash and prof.get("params") == {
+                k: q[k] for k in ("diamond_width", "tile_x", "threads_x", "cells_per_lane")}:
+            traffic = prof.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "mwd_row_kernel", "bytes_per_lup_model": round(bpl, 3),
+                "lups_per_launch": round(sum(per_launch) / len(per_launch)), "launches": n_launch,
+                "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
+
+    compare = None
+    if not args.no_compare:
+        compare = {}
+        nv = P.Sweep(w.stencil, "f64", w.nx, w.ny, w.nz, list(c), "naive")
+        n0, n1 = g0.clone(), g0.clone()
+        nv.run(n0, n1, w.T)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            ref = nv.run(n0, n1, w.T)
+        torch.cuda.synchronize()
+        compare["naive_f64_glups"] = round(lups * reps / (time.perf_counter() - t) / 1e9, 2)
+        # bit-exactness of the blocked run on the same input
+        m0, m1 = g0.clone(), g0.clone()
+        res64 = sw.run(m0, m1, w.T)
+        r0, r1 = g0.clone(), g0.clone()
+        ref = nv.run(r0, r1, w.T)
+        rel, mx, nd = P.error_norms(res64, ref, h, w.nx, w.ny, w.nz)
+        compare["blocked_vs_naive_f64_bitwise_diff"] = nd
+        nv.close()
+        del n0, n1, r0, r1
+        s32 = P.Sweep(w.stencil, "f32", w.nx, w.ny, w.nz, list(c), "mwd")
+        g32 = g0.to(torch.float32)
+        f0, f1 = g32.clone(), g32.clone()
+        s32.run(f0, f1, w.T)
+        best = None
+        for _ in range(reps):
+            # fresh input each time: the last run's result is the FP32 answer for u0
+            f0.copy_(g32)
+            f1.copy_(g32)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res32 = s32.run(f0, f1, w.T)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        compare["blocked_f32_glups"] = round(lups / best / 1e9, 2)
+        rel32, mx32, _ = P.error_norms(res32, res64, h, w.nx, w.ny, w.nz)
+        compare["f32_rel_l2_vs_f64"] = float("%.3e" % rel32)
+        compare["f32_max_abs_vs_f64"] = float("%.3e" % mx32)
+        compare["f32_params"] = s32.info()["params"]
+        s32.close()
+        del f0, f1, g32, m0, m1
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import sweep as O
+        a0 = u0.copy()
+        a1 = u0.copy()
+        t = time.perf_counter()
+        O.sweep(w.stencil, a0, a1, 2, c, None)
+        rate = w.nx * w.ny * w.nz * 2 / (time.perf_counter() - t)
+        # about ten seconds of oracle time, at most the whole run
+        t_s = int(max(2, min(w.T, 10.0 * rate / (w.nx * w.ny * w.nz))))
+        a0 = u0.copy()
+        a1 = u0.copy()
+        t = time.perf_counter()
+        O.sweep(w.stencil, a0, a1, t_s, c, None)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(w.nx * w.ny * w.nz * t_s / dt / 1e9, 4), "unit": "GLUP/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": "%dx%dx%d 7-point constant FP64, %d of the %d steps, plain C sweep (OpenMP over z), %.1f s"
+                         % (w.nx, w.ny, w.nz, t_s, w.T, dt)}
+
+    out = {
+        "metric": "GLUP/s per stencil at 1 GPU + % HBM roofline; blocked vs naive, FP32 vs FP64",
+        "value": round(value, 2),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "stencil": "7-point constant (c0=0.4, c1=0.1)",
+                   "grid": [w.nx, w.ny, w.nz], "halo": h, "T": w.T, "algo": "mwd", "params": q,
+                   "lds_bytes": info["lds_bytes"], "median_run_ms": round(sorted(times)[len(times) // 2] * 1e3, 3),
+                   "kernel_source_hash": src_hash},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "compare": compare,
+    }
+    print(json.dumps(out), flush=True)
+    sw.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,16 @@ int girih_plan_info(girih_plan_t plan, girih_params* params, int64_t* lds_bytes,
 /* Change the parameters of an existing plan (validated like girih_plan). */
 int girih_plan_set_params(girih_plan_t plan, const girih_params* params);
 
+/* Launch timing (diagnostics, used by the benchmark's roofline figure).
+ * With timing enabled, girih_run brackets every sweep-kernel launch (one per
+ * diamond row for MWD, one per step for NAIVE; not the halo copies) with a
+ * pair of HIP events on hip_stream.  girih_timing waits for the last event of
+ * the most recent run and returns the number of such launches and the sum of
+ * their durations in milliseconds (0 launches if timing is off).  The tuner's
+ * own test runs are not recorded. */
+int girih_set_timing(girih_plan_t plan, int32_t enable);
+int girih_timing(girih_plan_t plan, int32_t* n_launches, double* kernel_ms);
+
 void girih_destroy(girih_plan_t plan);
 
 const char* girih_strerror(int code);

@@ -81,6 +81,10 @@ struct girih_plan_s {
     size_t scratch_bytes = 0;
     int scratch_device = -1;
     Tuning tuning;
+    // per-launch timing of the sweep kernels (girih_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> events;   // pairs: before / after each sweep launch
+    int n_timed = 0;
 };
 
 namespace {
@@ -200,6 +204,23 @@ GridDesc desc_of(const girih_plan_s* p) {
         if ((x) != hipSuccess) return GIRIH_E_HIP;  \
     } while (0)
 
+// Launch one sweep kernel; with timing on, bracket it with a pair of events
+// on the same stream.
+int timed_launch(girih_plan_s* p, const void* args, dim3 grid, dim3 block, hipStream_t s) {
+    if (!p->timing) return p->kern->launch(args, grid, block, s) == hipSuccess ? GIRIH_OK : GIRIH_E_HIP;
+    const size_t need = 2 * (size_t)(p->n_timed + 1);
+    while (p->events.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return GIRIH_E_HIP;
+        p->events.push_back(e);
+    }
+    HIPCHK(hipEventRecord(p->events[2 * p->n_timed], s));
+    HIPCHK(p->kern->launch(args, grid, block, s));
+    HIPCHK(hipEventRecord(p->events[2 * p->n_timed + 1], s));
+    ++p->n_timed;
+    return GIRIH_OK;
+}
+
 template <typename Real>
 int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s) {
     NaiveArgs<Real> a;
@@ -213,7 +234,8 @@ int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs,
     for (int64_t t = 0; t < T; ++t) {
         a.V = b[t & 1];
         a.U = b[(t + 1) & 1];
-        HIPCHK(p->kern->launch(&a, grid, block, s));
+        const int rc = timed_launch(p, &a, grid, block, s);
+        if (rc) return rc;
     }
     return GIRIH_OK;
 }
@@ -288,7 +310,8 @@ int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, i
         a.c_first = off;
         const int64_t n_diamonds = (ny + dw / 2 - off + dw - 1) / dw;
         const dim3 grid((unsigned)p->n_xchunks, (unsigned)n_diamonds);
-        HIPCHK(p->kern->launch(&a, grid, block, s));
+        rc = timed_launch(p, &a, grid, block, s);
+        if (rc) return rc;
         in_user = !in_user;
     }
     return GIRIH_OK;
@@ -519,6 +542,7 @@ int girih_run(girih_plan_t p, void* buf0, void* buf1, const void* const* coef_ar
     for (int m = 0; m < n_coef; ++m)
         if (!coef_arrays[m]) return GIRIH_E_INVALID;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    p->n_timed = 0;   // the timing record covers the last run
     int rc = run_any(p, buf0, buf1, coef_arrays, T, s);
     if (rc) return rc;
     if (result_index) *result_index = (int32_t)(T & 1);
@@ -551,6 +575,13 @@ int girih_tune(girih_plan_t p, int32_t mode, int64_t T, double max_seconds, void
     else cands = p->algo == GIRIH_MWD ? mwd_candidates(p) : naive_candidates(p);
     if (cands.empty()) return GIRIH_E_UNSUPPORTED;
     const girih_params saved = p->params;
+    // the tuner's test runs are not recorded by the launch timing
+    struct TimingOff {
+        girih_plan_s* p;
+        bool was;
+        ~TimingOff() { p->timing = was; p->n_timed = 0; }
+    } timing_off{p, p->timing};
+    p->timing = false;
     TuneBufs bufs;
     int rc = alloc_tune_bufs(p, bufs, s);
     if (rc) return rc;
@@ -674,8 +705,33 @@ int girih_plan_info(girih_plan_t p, girih_params* params, int64_t* lds_bytes, do
     return GIRIH_OK;
 }
 
+int girih_set_timing(girih_plan_t p, int32_t enable) {
+    if (!p) return GIRIH_E_INVALID;
+    p->timing = enable != 0;
+    p->n_timed = 0;
+    return GIRIH_OK;
+}
+
+int girih_timing(girih_plan_t p, int32_t* n_launches, double* kernel_ms) {
+    if (!p || !n_launches || !kernel_ms) return GIRIH_E_INVALID;
+    *n_launches = 0;
+    *kernel_ms = 0;
+    if (!p->timing || p->n_timed == 0) return GIRIH_OK;
+    if (hipEventSynchronize(p->events[2 * p->n_timed - 1]) != hipSuccess) return GIRIH_E_HIP;
+    double total = 0;
+    for (int i = 0; i < p->n_timed; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, p->events[2 * i], p->events[2 * i + 1]) != hipSuccess) return GIRIH_E_HIP;
+        total += ms;
+    }
+    *n_launches = p->n_timed;
+    *kernel_ms = total;
+    return GIRIH_OK;
+}
+
 void girih_destroy(girih_plan_t p) {
     if (!p) return;
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
         if (p->scratch[i]) (void)hipFree(p->scratch[i]);
     if (p->halo_flag) (void)hipFree(p->halo_flag);

@@ -75,6 +75,8 @@ SIGNATURES = {
     "girih_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "girih_plan_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams)]),
+    "girih_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "girih_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "girih_destroy": (None, [ctypes.c_void_p]),
     "girih_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "girih_error_norms": (ctypes.c_int, [ctypes.POINTER(GirihGrid), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
@@ -183,6 +185,17 @@ def girih_plan_info(plan):
 def girih_plan_set_params(plan, params):
     p = params if isinstance(params, GirihParams) else GirihParams.from_dict(params)
     _check(_lib().girih_plan_set_params(plan, ctypes.byref(p)), "girih_plan_set_params")
+
+
+def girih_set_timing(plan, enable):
+    _check(_lib().girih_set_timing(plan, 1 if enable else 0), "girih_set_timing")
+
+
+def girih_timing(plan):
+    n = ctypes.c_int32(0)
+    ms = ctypes.c_double(0)
+    _check(_lib().girih_timing(plan, ctypes.byref(n), ctypes.byref(ms)), "girih_timing")
+    return n.value, ms.value
 
 
 def girih_destroy(plan):

@@ -80,6 +80,14 @@ class Sweep:
         params, lds, bpl = G.girih_plan_info(self.plan)
         return {"params": params, "lds_bytes": lds, "model_bytes_per_lup": bpl}
 
+    def set_timing(self, enable=True):
+        """Bracket every sweep-kernel launch of later runs with HIP events."""
+        G.girih_set_timing(self.plan, enable)
+
+    def timing(self):
+        """(launches, total kernel milliseconds) of the most recent run."""
+        return G.girih_timing(self.plan)
+
     def set_params(self, params):
         G.girih_plan_set_params(self.plan, params)
 
