@@ -110,7 +110,9 @@ struct DiamondShape {
     }
     // LDS row of (stage level k, local row j) is srow0(k) + j
     static constexpr int srow0(int k) { return sbase(k) - sl_lo(k); }
-    static constexpr int STAGE_ROWS = sbase(L - 1);
+    // levels 0..L-2 (read by the level above) and level L-1, whose 2R rows are
+    // staged only to be stored
+    static constexpr int STAGE_ROWS = sbase(L);
     // the band of levels a partner (row B) can hold
     static constexpr int BMIN = H / 2;
     static constexpr int KB_LO = BMIN + 1;
@@ -255,7 +257,8 @@ enum : int {
     F_D1_A = 1 << 7, F_D2_A = 1 << 8, F_D1_B = 1 << 9, F_D2_B = 1 << 10,   // stage duties
     F_O_A = 1 << 11, F_O_B = 1 << 12,           // out-of-span duty
     F_PV_A = 1 << 13, F_PV_B = 1 << 14,         // parity of duty level kv's time level
-    F_PT = 1 << 15                              // parity of t_c
+    F_PT = 1 << 15,                             // parity of t_c
+    F_COPY_A = 1 << 16, F_COPY_B = 1 << 17      // row inside the grid without a level in this row
 };
 
 // Every wave runs the same code: its two rows are laid out as one list of at
@@ -372,7 +375,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                       (cmpB ? F_CMP_B : 0) | (d1A ? F_D1_A : 0) | (d2A ? F_D2_A : 0) | (d1B ? F_D1_B : 0) |
                       (d2B ? F_D2_B : 0) | (joA > -1000 ? F_O_A : 0) | (joB > -1000 ? F_O_B : 0) |
                       (((t_c - H + kvA + 1) & 1) ? F_PV_A : 0) | (((t_c - H + kvB + 1) & 1) ? F_PV_B : 0) |
-                      ((t_c & 1) ? F_PT : 0);
+                      ((t_c & 1) ? F_PT : 0) | (inA && !cmpA ? F_COPY_A : 0) | (inB && !cmpB ? F_COPY_B : 0);
     auto rowb_of = [&](int j) -> uint32_t { return (uint32_t)((ybase + j + hh) * pitchx * SB); };
     auto lds_row = [&](int k, int j) -> int { return (srow0_rt<Sh>(k) + j) * XLP + R; };   // element index
     const uint32_t lane_b = (uint32_t)((cb + lane) * SB);
@@ -405,8 +408,8 @@ mwd_row_kernel(MwdArgs<Real> a) {
     // window (plane of its level, its row); masks over slots.
     constexpr int CORNER = (R * XLP + R) * SB;   // from the corner to the cell itself
     const uint32_t spare = (uint32_t)(Sh::STAGE_ROWS * XLP * SB);
-    uint32_t lcs[NS], gos[NS];
-    uint32_t cmS = 0, stoS = 0, stcS = 0, parS = 0;
+    uint32_t lcs[NS], gos[S::NCOEF > 0 ? NS : 1];
+    uint32_t cmS = 0;
     static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         const bool isB = s >= sB;
@@ -414,15 +417,41 @@ mwd_row_kernel(MwdArgs<Real> a) {
         const bool valid = isB ? (cmpB && t < nB) : cmpA;
         const int k = (isB ? baseB : baseA) + t;
         const int j = isB ? jB : jA;
-        const int kf = isB ? kfB : kfA, kl = isB ? klB : klA;
-        lcs[s] = in_vgpr(valid && k <= L - 2 ? (uint32_t)(lds_row(k, j) * SB - CORNER) : spare) + lane_b;
-        gos[s] = in_vgpr(valid ? (uint32_t)(R * (L - k)) * plane_b + rowb_of(j) : 0u);
-        const bool cmp = valid && t >= 1;
-        cmS |= cmp ? 1u << s : 0u;
-        stoS |= cmp && k >= kl - 1 ? 1u << s : 0u;
-        stcS |= cmp && kf == kl ? 1u << s : 0u;
-        parS |= ((p0 ^ k ^ 1) & 1) ? 1u << s : 0u;
+        lcs[s] = in_vgpr(valid ? (uint32_t)(lds_row(k, j) * SB - CORNER) : spare) + lane_b;
+        if constexpr (S::NCOEF > 0) gos[s] = in_vgpr(valid ? (uint32_t)(R * (L - k)) * plane_b + rowb_of(j) : 0u);
+        cmS |= valid && t >= 1 ? 1u << s : 0u;
     });
+    // Stores: the state a row leaves is its last two levels kl and kl-1 (for a
+    // row with one level, kl-1 is its input level).  At step zs the stage row
+    // of level k holds plane zs - R*(k+1), so the stores read the two stage
+    // rows back after the barrier: every plane of each level passes through
+    // the stage once.  Per row the even and the odd one of the two levels
+    // (time levels of opposite parity) go to out[p0^1] and out[p0].
+    // Store i: 0 = A even, 1 = A odd, 2 = B even, 3 = B odd.
+    uint32_t stl[4], sgo[4][VX];
+    int stk[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool isB = i >= 2;
+        const bool cmp = isB ? cmpB : cmpA;
+        const int kl = isB ? klB : klA;
+        const int k = ((kl & 1) == (i & 1)) ? kl : kl - 1;   // level of this parity
+        const int j = isB ? jB : jA;
+        stk[i] = cmp ? k : -1000;
+        stl[i] = in_vgpr(cmp ? (uint32_t)(lds_row(k, j) * SB) : spare) + lane_b;
+        const uint32_t u = in_vgpr(cmp ? (uint32_t)(R * (L - k - 1)) * plane_b + rowb_of(j) : 0u);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) sgo[i][v] = cmp ? ((u + xb[v]) | kill[v]) : DROP;
+    }
+    // rows that compute no level copy both input levels: plane zs is R*L
+    // planes above the window base
+    uint32_t cpo[2][VX];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const uint32_t u = in_vgpr((uint32_t)(R * L) * plane_b + rowb_of(t == 0 ? jA : jB));
+#pragma unroll
+        for (int v = 0; v < VX; ++v) cpo[t][v] = u + xb[v];
+    }
     const uint32_t maskA = bit_range(0, sB - 1);
 
     // Two instances of the sweep: zero Dirichlet halo (halo cells are
@@ -447,7 +476,9 @@ mwd_row_kernel(MwdArgs<Real> a) {
 #pragma unroll
         for (int v = 0; v < VX; ++v) hz[v] = ZH && edge_x && xh[v];
 
-        const int nzs = nz + R * (L - 1);   // wavefront steps end here
+        // wavefront steps end here: the last plane of level L-1 is computed at
+        // step nz-1 + R*(L-1) and passes through the stage R steps later
+        const int nzs = nz + R * L;
         // byte offset of plane q from the array base
         auto plane_off = [&](int q) -> int64_t { return (int64_t)(q + hh) * (int64_t)plane_b; };
         auto at = [](const Real* base, int64_t off) -> const Real* {
@@ -567,9 +598,23 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 const int f = (int)fresh_s((uint32_t)flags);
                 // window of this step: planes [zs - R*L, zs]
                 const int64_t e0b = plane_off(zs - R * L);
-                Real* const ob0p = atw(a.out[0], e0b);
-                Real* const ob1p = atw(a.out[1], e0b);
-                const uint32_t cm = fresh_s(cmS), sto = fresh_s(stoS), stc = fresh_s(stcS), par = fresh_s(parS);
+                {
+                    // the rows' last two levels, from the stage (see above)
+                    const __amdgpu_buffer_rsrc_t rs_even = raw_rsrc(atw(a.out[p0 ^ 1], e0b));
+                    const __amdgpu_buffer_rsrc_t rs_odd = raw_rsrc(atw(a.out[p0], e0b));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        uint32_t zd = 0;
+                        if constexpr (!STEADY) {
+                            const int q = zs - R * (stk[i] + 1);
+                            zd = q >= 0 && q < nz ? 0u : DROP;
+                        }
+#pragma unroll
+                        for (int v = 0; v < VX; ++v)
+                            buf_store((i & 1) ? rs_odd : rs_even, sgo[i][v] | zd, lds(stl[i] + 64 * v * SB));
+                    }
+                }
+                const uint32_t cm = fresh_s(cmS);
                 const int sb = (int)fresh_s((uint32_t)sB);
                 uint32_t zS = 0xffffffffu;   // slots whose level's plane zs - R*k lies inside the grid
                 if constexpr (!STEADY) {
@@ -577,8 +622,27 @@ mwd_row_kernel(MwdArgs<Real> a) {
                     const int klz = zs - nz >= 0 ? (zs - nz) / R + 1 : 0;
                     zS = (bit_range(klz - baseA, khz - baseA) & maskA) | (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA);
                 }
-                const uint32_t stm = (sto | stc) & zS;
                 Real prev[VX];
+                // x/y neighbours of a slot, read from the stage one slot ahead
+                // of its use (a one-deep software pipeline: deeper prefetching
+                // would hold too many registers)
+                Real nb[2][4 * R][VX];
+                auto load_nb = [&](auto tc) __attribute__((always_inline)) {
+                    constexpr int t = decltype(tc)::value;
+                    const uint32_t lb = lcs[t - 1];     // corner of (level - 1, row)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        const uint32_t c0 = lb + 64 * v * SB + CORNER;
+#pragma unroll
+                        for (int r = 1; r <= R; ++r) {
+                            nb[t & 1][r - 1][v] = lds(c0 + r * SB);
+                            nb[t & 1][R + r - 1][v] = lds(c0 - r * SB);
+                            nb[t & 1][2 * R + r - 1][v] = lds(c0 + r * XLP * SB);
+                            nb[t & 1][3 * R + r - 1][v] = lds(c0 - r * XLP * SB);
+                        }
+                    }
+                };
+                load_nb(std::integral_constant<int, 1>{});
                 static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
                     constexpr int s = decltype(sc)::value;
                     Real nv[VX];
@@ -587,24 +651,22 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         for (int v = 0; v < VX; ++v) nv[v] = vcA[v];
                     } else {
                         // every slot is computed (unused slots compute values nobody reads)
-                        const uint32_t lb = lcs[s - 1];     // corner of (level - 1, row)
                         // a computed level whose plane lies inside the grid (unused
                         // slots never count: their offsets are not theirs to load)
                         const bool zv = ((cm & zS) >> s) & 1u;
-                        Real cen[VX];
+                        if constexpr (s + 1 < NS) load_nb(std::integral_constant<int, s + 1>{});
 #pragma unroll
                         for (int v = 0; v < VX; ++v) {
-                            const uint32_t c0 = lb + 64 * v * SB;
                             Nbhd<Real, R> n;
                             n.c = ring[s - 1][P(R)][v];
 #pragma unroll
                             for (int r = 1; r <= R; ++r) {
                                 n.zm[r - 1] = ring[s - 1][P(R - r)][v];
                                 n.zp[r - 1] = r == R ? prev[v] : ring[s - 1][P(R + r)][v];
-                                n.xp[r - 1] = lds(c0 + CORNER + r * SB);
-                                n.xm[r - 1] = lds(c0 + CORNER - r * SB);
-                                n.yp[r - 1] = lds(c0 + CORNER + r * XLP * SB);
-                                n.ym[r - 1] = lds(c0 + CORNER - r * XLP * SB);
+                                n.xp[r - 1] = nb[s & 1][r - 1][v];
+                                n.xm[r - 1] = nb[s & 1][R + r - 1][v];
+                                n.yp[r - 1] = nb[s & 1][2 * R + r - 1][v];
+                                n.ym[r - 1] = nb[s & 1][3 * R + r - 1][v];
                             }
                             Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
                             if constexpr (S::NCOEF > 0) {
@@ -622,7 +684,6 @@ mwd_row_kernel(MwdArgs<Real> a) {
                                 }
                             }
                             nv[v] = S::apply(n, a.coef.k, cf);
-                            cen[v] = n.c;
                         }
                         if constexpr (!STEADY) {
                             // a level whose plane is a halo plane (or beyond) holds the halo
@@ -649,17 +710,6 @@ mwd_row_kernel(MwdArgs<Real> a) {
 #pragma unroll
                             for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
                         }
-                        // the last two levels of each row (and the input level of a
-                        // row that computes one level) go to the output pair
-                        if ((stm >> s) & 1u) {
-                            const bool podd = (par >> s) & 1u;
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) {
-                                const uint32_t so = (gos[s] + xb[v]) | kill[v];
-                                if ((sto >> s) & 1u) buf_store(raw_rsrc(podd ? ob1p : ob0p), so, nv[v]);
-                                if ((stc >> s) & 1u) buf_store(raw_rsrc(podd ? ob0p : ob1p), so, cen[v]);
-                            }
-                        }
                         // slot s-1's ring takes its newest plane
 #pragma unroll
                         for (int v = 0; v < VX; ++v) {
@@ -673,7 +723,14 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         }
                     }
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) prev[v] = nv[v];
+                    for (int v = 0; v < VX; ++v) {
+                        // pin the slot's result here: the arithmetic of a slot
+                        // must not sink below later slots' reads, whose results
+                        // would otherwise all be held in registers at once
+                        asm volatile("" : "+v"(nv[v]));
+                        prev[v] = nv[v];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 });
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
@@ -686,19 +743,16 @@ mwd_row_kernel(MwdArgs<Real> a) {
                     }
                 }
                 // rows of this diamond with no level in this row: carry both levels
-                if (zs >= 0 && zs < nz) {
+                if ((f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
+                    const __amdgpu_buffer_rsrc_t o0 = raw_rsrc(atw(a.out[0], e0b)), o1 = raw_rsrc(atw(a.out[1], e0b));
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        const bool in_row = t == 0 ? (f & F_IN_A) != 0 : (f & F_IN_B) != 0;
-                        const bool cmp = t == 0 ? (f & F_CMP_A) != 0 : (f & F_CMP_B) != 0;
-                        if (in_row && !cmp) {
-                            const int64_t ro = plane_off(zs) + (t == 0 ? rowb_of(jA) : rowb_of(jB));
+                        if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
 #pragma unroll
                             for (int v = 0; v < VX; ++v) {
-                                if (!kill[v]) {
-                                    st_at(atw(a.out[0], ro), xb[v], ld_at(at(a.in[0], ro), xb[v]));
-                                    st_at(atw(a.out[1], ro), xb[v], ld_at(at(a.in[1], ro), xb[v]));
-                                }
+                                const uint32_t o = cpo[t][v];
+                                buf_store(o0, o | kill[v], ld_at(at(a.in[0], e0b), o));
+                                buf_store(o1, o | kill[v], ld_at(at(a.in[1], e0b), o));
                             }
                         }
                     }
@@ -709,8 +763,9 @@ mwd_row_kernel(MwdArgs<Real> a) {
 
         // the sweep starts 2R steps early so that the input rings of rows
         // entering at level 1 hold the halo planes -R..-1; steps [zA, zB) are
-        // steady: every level's plane zs - R*k (k = 0..L-1) is inside the grid
-        const int zA = ((R * (L - 1) + UNR - 1) / UNR) * UNR;
+        // steady: every level's plane zs - R*k (k = 0..L-1) and every stored
+        // plane zs - R*(k+1) is inside the grid
+        const int zA = ((R * L + UNR - 1) / UNR) * UNR;
         const int zB = (nz / UNR) * UNR > zA ? (nz / UNR) * UNR : zA;
         {
             // first loads: the inputs of step -RING

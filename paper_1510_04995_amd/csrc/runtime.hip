@@ -112,14 +112,15 @@ const KernelEntry* find_naive(int st, int dt) {
 // Default MWD shape per radius and element size (diamond width, cells per
 // lane, waves along x); the tuner replaces it per problem.
 void default_mwd(int R, int dtype, int& dw, int& vx, int& wx) {
+    (void)dtype;
     if (R == 1) {
-        dw = dtype == GIRIH_F64 ? 12 : 16;
+        dw = 12;
         vx = 1;
         wx = 2;
     } else {
         dw = 16;
         vx = 1;
-        wx = 2;
+        wx = 1;
     }
 }
 
