@@ -165,9 +165,15 @@ struct MwdKernel {
     static constexpr int XLP = XL + 2 * R;      // LDS row stride (R guard cells per side)
     static constexpr int HX = R * (L - 1);      // redundant x halo per side
     static constexpr int XOWN_MAX = XL - 2 * HX;
-    // stage rows plus 2R+1 spare rows that absorb the stage writes and reads of
-    // slots without a stage row
-    static constexpr int LDS_ROWS = Sh::STAGE_ROWS + 2 * R + 1;
+    // one stage buffer: stage rows plus 2R+1 spare rows that absorb the stage
+    // writes and reads of slots without a stage row
+    static constexpr int BUF_ROWS = Sh::STAGE_ROWS + 2 * R + 1;
+    static constexpr int BUF_BYTES = BUF_ROWS * XLP * (int)sizeof(Real);
+    // Two stage buffers (even and odd wavefront steps) when they fit in the
+    // 160 KiB of LDS a workgroup may hold: a step then needs one barrier
+    // (between staging and compute) instead of two.
+    static constexpr bool DB = 2 * BUF_BYTES <= 163840;
+    static constexpr int LDS_ROWS = BUF_ROWS * (DB ? 2 : 1);
     static constexpr int LDS_BYTES = LDS_ROWS * XLP * (int)sizeof(Real);
     static constexpr int RING = 2 * R;
 };
@@ -283,7 +289,11 @@ mwd_row_kernel(MwdArgs<Real> a) {
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
     constexpr int NS = L + 2;
-    constexpr int UNR = RING <= 2 ? RING : 1;
+    // steps unrolled per loop iteration: two (the ring phases for R = 1, the
+    // two stage buffers, and the two sets of prefetch registers)
+    constexpr int UNR = 2;
+    // HBM inputs are loaded PD = 2 steps before the step that uses them
+    constexpr int PD = 2;
     constexpr int SB = (int)sizeof(Real);
     static_assert(NS <= 32, "slot masks are 32-bit");
     __shared__ Real stage[KK::LDS_ROWS * XLP];
@@ -379,30 +389,24 @@ mwd_row_kernel(MwdArgs<Real> a) {
     auto rowb_of = [&](int j) -> uint32_t { return (uint32_t)((ybase + j + hh) * pitchx * SB); };
     auto lds_row = [&](int k, int j) -> int { return (srow0_rt<Sh>(k) + j) * XLP + R; };   // element index
     const uint32_t lane_b = (uint32_t)((cb + lane) * SB);
-    // per-lane LDS byte addresses of the duty rows
-    auto lds_addr = [&](int k, int j) -> uint32_t { return in_vgpr((uint32_t)(lds_row(k, j) * SB)) + lane_b; };
-    const uint32_t lA1 = lds_addr(kvA, jA), lA2 = lds_addr(kvA - 1, jA), lB1 = lds_addr(kvB, jB),
-                   lB2 = lds_addr(kvB - 1, jB), lOA = lds_addr(H - 1, joA), lOB = lds_addr(H - 1, joB);
-    // Per-lane byte offsets of the prefetch streams from the base of the next
-    // step's window (plane zs + 1 - R*L): a stream at depth dz reads plane
-    // zs + 1 - R*dz of its row.
-    auto fo_of = [&](int dz, int j, uint32_t (&o)[VX]) {
-        const uint32_t u = in_vgpr((uint32_t)(R * (L - dz)) * plane_b + rowb_of(j));
-#pragma unroll
-        for (int v = 0; v < VX; ++v) o[v] = u + xb[v];
-    };
-    uint32_t foA[VX], foA1[VX], foB[VX], foB1[VX], foOA[VX], foOB[VX];
-    fo_of(kvA < 0 ? 0 : kvA, jA, foA);
-    fo_of(kvA < 0 ? 0 : kvA + 1, jA, foA1);
-    fo_of(kvB < 0 ? 0 : kvB, jB, foB);
-    fo_of(kvB < 0 ? 0 : kvB + 1, jB, foB1);
-    fo_of(H, joA > -1000 ? joA : jA, foOA);
-    fo_of(H, joB > -1000 ? joB : jB, foOB);
+    // LDS byte addresses (wave-uniform part; a lane adds lane_b) of the duty
+    // rows, and byte offsets (uniform part; a lane adds its x offset) of the
+    // prefetch streams from the base of their step's window (plane
+    // zs + PD - R*L): a stream at depth dz reads plane zs + PD - R*dz of its row.
+    // Kept uniform, so they cost scalar rather than vector registers.
+    auto fo_of = [&](int dz, int j) -> uint32_t { return (uint32_t)(R * (L - dz)) * plane_b + rowb_of(j); };
+    const uint32_t uA2 = (uint32_t)(lds_row(kvA - 1, jA) * SB), uB2 = (uint32_t)(lds_row(kvB - 1, jB) * SB),
+                   uOA = (uint32_t)(lds_row(H - 1, joA) * SB), uOB = (uint32_t)(lds_row(H - 1, joB) * SB);
+    const uint32_t foA = fo_of(kvA < 0 ? 0 : kvA, jA), foB = fo_of(kvB < 0 ? 0 : kvB, jB),
+                   foOA = fo_of(H, joA > -1000 ? joA : jA), foOB = fo_of(H, joB > -1000 ? joB : jB);
 
     // ---- slot layout -----------------------------------------------------------
     const int sB = cmpA ? klA - kfA + 2 : 1;   // first slot of row B
     const int nB = cmpB ? klB - kfB + 2 : 1;
-    const int baseA = kfA - 1, baseB = kfB - 1;   // level of each row's first slot
+    // Level of each row's first slot: its input level kf-1 = kv.  A row that
+    // computes nothing but owes level kv (d1) keeps it in that slot too: the
+    // slot is loaded and staged exactly like an input ring.
+    const int baseA = cmpA ? kfA - 1 : kvA, baseB = cmpB ? kfB - 1 : kvB;
     // LDS byte address (per lane) of the corner (row - R, column - R) of the
     // slot's stage row, and the slot's global byte offset within the step's
     // window (plane of its level, its row); masks over slots.
@@ -414,7 +418,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
         constexpr int s = decltype(sc)::value;
         const bool isB = s >= sB;
         const int t = isB ? s - sB : s;
-        const bool valid = isB ? (cmpB && t < nB) : cmpA;
+        const bool valid = isB ? (cmpB ? t < nB : (d1B && t == 0)) : (cmpA || d1A);
         const int k = (isB ? baseB : baseA) + t;
         const int j = isB ? jB : jA;
         lcs[s] = in_vgpr(valid ? (uint32_t)(lds_row(k, j) * SB - CORNER) : spare) + lane_b;
@@ -465,8 +469,10 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
                     const int y = ybase + j;
                     if ((y >= -R && y < 0) || (y >= ny && y < ny + R)) {
-                        Real* sp = stage + lds_row(k, j) - R;
-                        for (int col = threadIdx.x; col < XLP; col += KK::NT) sp[col] = Real(0);
+                        for (int b = 0; b < (KK::DB ? 2 : 1); ++b) {
+                            Real* sp = stage + b * KK::BUF_ROWS * XLP + lds_row(k, j) - R;
+                            for (int col = threadIdx.x; col < XLP; col += KK::NT) sp[col] = Real(0);
+                        }
                     }
                 }
             }
@@ -495,7 +501,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
             for (int v = 0; v < VX; ++v) lds(la + 64 * v * SB) = hz[v] ? Real(0) : src[v];
         };
         // x-halo columns of a staged computed row when the halo is not zero
-        auto fix_halo_cols = [&](int li, int q, int y) {
+        auto fix_halo_cols = [&](int li, int q, int y) {   // li: element index, buffer included
             if (q < -R || q >= nz + R) return;
             const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
 #pragma unroll
@@ -503,11 +509,51 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 if (xh[v]) stage[li + cb + lane + 64 * v] = ld_at(base, xb[v]);
         };
 
+        // Loads of step zs + PD's inputs (see the streams above); with a
+        // staging function, duty registers are first staged.
+        auto prefetch = [&](int zs, bool steady, Real (&vA)[VX], Real (&vB)[VX], Real (&dA2)[VX], Real (&dB2)[VX],
+                            Real (&rA)[VX], Real (&rB)[VX], auto&& stage_fn) __attribute__((always_inline)) {
+            const int f = (int)fresh_s((uint32_t)flags);
+            // per-lane offsets, formed here from the uniform parts (fresh
+            // copies keep the compiler from hoisting them into registers
+            // that stay live across the loop)
+            uint32_t oA[VX], oB[VX], oOA[VX], oOB[VX];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                oA[v] = fresh_s(foA) + xb[v];
+                oB[v] = fresh_s(foB) + xb[v];
+                oOA[v] = fresh_s(foOA) + xb[v];
+                oOB[v] = fresh_s(foOB) + xb[v];
+            }
+            const int64_t nb = plane_off(zs + PD - R * L);
+            const Real* fb0 = at(a.in[0], nb);
+            const Real* fb1 = at(a.in[1], nb);
+            auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[VX]) __attribute__((always_inline)) {
+                if (!steady) {
+                    const int q = zs + PD - R * dz;
+                    if (q < -R || q >= nz + R) return;
+                }
+                const Real* base = odd ? fb1 : fb0;
+#pragma unroll
+                for (int v = 0; v < VX; ++v) dst[v] = ld_at(base, o[v]);
+            };
+            if (f & (F_CMP_A | F_D1_A)) fetch(f & F_PV_A, kvA, oA, vA);
+            if (f & (F_CMP_B | F_D1_B)) fetch(f & F_PV_B, kvB, oB, vB);
+            if (f & F_D2_A) { stage_fn(fresh_s(uA2) + lane_b, dA2); fetch(!(f & F_PV_A), kvA, oA, dA2); }
+            if (f & F_D2_B) { stage_fn(fresh_s(uB2) + lane_b, dB2); fetch(!(f & F_PV_B), kvB, oB, dB2); }
+            if (f & F_O_A) { stage_fn(fresh_s(uOA) + lane_b, rA); fetch(f & F_PT, H, oOA, rA); }
+            if (f & F_O_B) { stage_fn(fresh_s(uOB) + lane_b, rB); fetch(f & F_PT, H, oOB, rB); }
+        };
+
         Real ring[NS][RING][VX];
-        Real vnA[VX], vnB[VX], p1A[VX], p1B[VX], p2A[VX], p2B[VX], poA[VX], poB[VX];
+        // Prefetch registers, one set per step parity.  qA/qB: the input level
+        // kv of a row (its input ring);
+        // p2: duty level kv-1; po: the out-of-span row.
+        Real qA[2][VX], qB[2][VX], p2A[2][VX], p2B[2][VX], poA[2][VX], poB[2][VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            vnA[v] = vnB[v] = p1A[v] = p1B[v] = p2A[v] = p2B[v] = poA[v] = poB[v] = Real(0);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) qA[c][v] = qB[c][v] = p2A[c][v] = p2B[c][v] = poA[c][v] = poB[c][v] = Real(0);
 #pragma unroll
             for (int m = 0; m < RING; ++m) {
 #pragma unroll
@@ -519,6 +565,9 @@ mwd_row_kernel(MwdArgs<Real> a) {
         auto step = [&](auto phc, auto steadyc, int zs) __attribute__((always_inline)) {
             constexpr int ph = decltype(phc)::value;
             constexpr bool STEADY = decltype(steadyc)::value;
+            // stage buffer of this step (steps start at an even zs, so ph = zs mod 2)
+            constexpr uint32_t BOFF = KK::DB ? (uint32_t)(ph & 1) * KK::BUF_BYTES : 0u;
+            constexpr int BOFE = (int)BOFF / SB;
             // physical register of logical ring position m (0 = oldest plane)
             auto P = [](int m) { return UNR == RING ? (m + ph) % RING : m; };
             const bool live = STEADY || UNR == 1 || zs < nzs;   // uniform across the workgroup
@@ -529,7 +578,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
             }
             Real vcA[VX], vcB[VX];
 #pragma unroll
-            for (int v = 0; v < VX; ++v) { vcA[v] = vnA[v]; vcB[v] = vnB[v]; }
+            for (int v = 0; v < VX; ++v) { vcA[v] = qA[ph & 1][v]; vcB[v] = qB[ph & 1][v]; }
             // ---- A: stage every plane the levels read this step ------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
@@ -538,40 +587,24 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
                     constexpr int s = decltype(sc)::value;
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) lds(lcs[s] + CORNER + 64 * v * SB) = hz[v] ? Real(0) : ring[s][P(R)][v];
+                    for (int v = 0; v < VX; ++v) lds(lcs[s] + BOFF + CORNER + 64 * v * SB) = hz[v] ? Real(0) : ring[s][P(R)][v];
                 });
-                // prefetch of the next step's inputs: plane zs + 1 - R*dz of each
-                // stream; planes outside the haloed grid are skipped (no computing
-                // cell reads them; in the steady range every plane is inside).  A
-                // duty register is staged before its next load is issued.
-                const int64_t nb = plane_off(zs + 1 - R * L);
-                const Real* fb0 = at(a.in[0], nb);
-                const Real* fb1 = at(a.in[1], nb);
-                auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[VX]) __attribute__((always_inline)) {
-                    if constexpr (!STEADY) {
-                        const int q = zs + 1 - R * dz;
-                        if (q < -R || q >= nz + R) return;
-                    }
-                    const Real* base = odd ? fb1 : fb0;
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) dst[v] = ld_at(base, o[v]);
-                };
-                if (f & F_CMP_A) fetch(f & F_PV_A, kvA, foA, vnA);
-                if (f & F_CMP_B) fetch(f & F_PV_B, kvB, foB, vnB);
-                if (f & F_D1_A) { put(lA1, p1A); fetch(f & F_PV_A, kvA + 1, foA1, p1A); }
-                if (f & F_D1_B) { put(lB1, p1B); fetch(f & F_PV_B, kvB + 1, foB1, p1B); }
-                if (f & F_D2_A) { put(lA2, p2A); fetch(!(f & F_PV_A), kvA, foA, p2A); }
-                if (f & F_D2_B) { put(lB2, p2B); fetch(!(f & F_PV_B), kvB, foB, p2B); }
-                if (f & F_O_A) { put(lOA, poA); fetch(f & F_PT, H, foOA, poA); }
-                if (f & F_O_B) { put(lOB, poB); fetch(f & F_PT, H, foOB, poB); }
+                // loads for step zs + PD into this step's register set (its
+                // values are consumed above or copied to vcA/vcB): plane
+                // zs + PD - R*dz of each stream; planes outside the haloed grid
+                // are skipped (no computing cell reads them; in the steady range
+                // every plane is inside).  A duty register is staged before its
+                // next load is issued.
+                prefetch(zs, STEADY, qA[ph & 1], qB[ph & 1], p2A[ph & 1], p2B[ph & 1], poA[ph & 1], poB[ph & 1],
+                         [&](uint32_t la, const Real (&src)[VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
                 // non-zero halo, edge workgroups only: fixed values in halo columns
                 // of computed rows, and halo rows (latency exposed)
                 if (!ZH && (f & (F_EDGE_X | F_EDGE_Y))) {
                     if (f & F_EDGE_X) {
                         for (int k = kfA; k <= klA && k <= L - 2; ++k)
-                            fix_halo_cols(lds_row(k, jA), zs - R * (k + 1), ybase + jA);
+                            fix_halo_cols(lds_row(k, jA) + BOFE, zs - R * (k + 1), ybase + jA);
                         for (int k = kfB; k <= klB && k <= L - 2; ++k)
-                            fix_halo_cols(lds_row(k, jB), zs - R * (k + 1), ybase + jB);
+                            fix_halo_cols(lds_row(k, jB) + BOFE, zs - R * (k + 1), ybase + jB);
                     }
                     if (f & F_EDGE_Y) {
                         for (int k = wave; k < L - 1; k += KK::NWAVES) {
@@ -580,7 +613,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                                 const int q = zs - R * (k + 1);
                                 if (((y >= -R && y < 0) || (y >= ny && y < ny + R)) && q >= -R && q < nz + R) {
                                     const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
-                                    const int li = lds_row(k, j);
+                                    const int li = lds_row(k, j) + BOFE;
                                     for (int col = lane; col < KK::XL; col += 64) {
                                         const int x = x0 + col;
                                         const int xc = x < -R ? -R : (x >= nx + R ? nx + R - 1 : x);
@@ -611,7 +644,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         }
 #pragma unroll
                         for (int v = 0; v < VX; ++v)
-                            buf_store((i & 1) ? rs_odd : rs_even, sgo[i][v] | zd, lds(stl[i] + 64 * v * SB));
+                            buf_store((i & 1) ? rs_odd : rs_even, sgo[i][v] | zd, lds(stl[i] + BOFF + 64 * v * SB));
                     }
                 }
                 const uint32_t cm = fresh_s(cmS);
@@ -629,7 +662,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 Real nb[2][4 * R][VX];
                 auto load_nb = [&](auto tc) __attribute__((always_inline)) {
                     constexpr int t = decltype(tc)::value;
-                    const uint32_t lb = lcs[t - 1];     // corner of (level - 1, row)
+                    const uint32_t lb = lcs[t - 1] + BOFF;     // corner of (level - 1, row)
 #pragma unroll
                     for (int v = 0; v < VX; ++v) {
                         const uint32_t c0 = lb + 64 * v * SB + CORNER;
@@ -655,6 +688,8 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         // slots never count: their offsets are not theirs to load)
                         const bool zv = ((cm & zS) >> s) & 1u;
                         if constexpr (s + 1 < NS) load_nb(std::integral_constant<int, s + 1>{});
+                        // issue those reads before this slot's arithmetic
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int v = 0; v < VX; ++v) {
                             Nbhd<Real, R> n;
@@ -758,7 +793,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                     }
                 }
             }
-            __syncthreads();
+            if constexpr (!KK::DB) __syncthreads();   // with two buffers the next step's staging may overlap
         };
 
         // the sweep starts 2R steps early so that the input rings of rows
@@ -766,30 +801,14 @@ mwd_row_kernel(MwdArgs<Real> a) {
         // steady: every level's plane zs - R*k (k = 0..L-1) and every stored
         // plane zs - R*(k+1) is inside the grid
         const int zA = ((R * L + UNR - 1) / UNR) * UNR;
-        const int zB = (nz / UNR) * UNR > zA ? (nz / UNR) * UNR : zA;
-        {
-            // first loads: the inputs of step -RING
-            const int zs = -RING - 1;
-            const int f = (int)fresh_s((uint32_t)flags);
-            const int64_t nb = plane_off(zs + 1 - R * L);
-            const Real* fb0 = at(a.in[0], nb);
-            const Real* fb1 = at(a.in[1], nb);
-            auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[VX]) {
-                const int q = zs + 1 - R * dz;
-                if (q < -R || q >= nz + R) return;
-                const Real* base = odd ? fb1 : fb0;
-#pragma unroll
-                for (int v = 0; v < VX; ++v) dst[v] = ld_at(base, o[v]);
-            };
-            if (f & F_CMP_A) fetch(f & F_PV_A, kvA, foA, vnA);
-            if (f & F_CMP_B) fetch(f & F_PV_B, kvB, foB, vnB);
-            if (f & F_D2_A) fetch(!(f & F_PV_A), kvA, foA, p2A);
-            if (f & F_D2_B) fetch(!(f & F_PV_B), kvB, foB, p2B);
-            if (f & F_D1_A) fetch(f & F_PV_A, kvA + 1, foA1, p1A);
-            if (f & F_D1_B) fetch(f & F_PV_B, kvB + 1, foB1, p1B);
-            if (f & F_O_A) fetch(f & F_PT, H, foOA, poA);
-            if (f & F_O_B) fetch(f & F_PT, H, foOB, poB);
-        }
+        // (and the loads of step zs + PD stay inside the haloed grid: for R = 1
+        // the steady range ends one plane early)
+        const int zB0 = R >= PD ? nz : nz + R - PD;
+        const int zB = (zB0 / UNR) * UNR > zA ? (zB0 / UNR) * UNR : zA;
+        // first loads: the inputs of steps -RING and -RING + 1
+        auto no_stage = [](uint32_t, const Real (&)[VX]) {};
+        prefetch(-RING - PD, false, qA[0], qB[0], p2A[0], p2B[0], poA[0], poB[0], no_stage);
+        prefetch(-RING - PD + 1, false, qA[1], qB[1], p2A[1], p2B[1], poA[1], poB[1], no_stage);
         __syncthreads();
         using General = std::integral_constant<bool, false>;
         using Steady = std::integral_constant<bool, true>;
