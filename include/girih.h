@@ -191,6 +191,39 @@ const char* girih_strerror(int code);
 int girih_error_norms(const girih_grid* grid, girih_dtype dtype_a, const void* a, girih_dtype dtype_b,
                       const void* b, void* hip_stream, double out[4]);
 
+/* Cost model of the tuner: a fully connected network in FP32 that predicts
+ * the log throughput of a tuner candidate from its features (the feature list
+ * is in paper_1510_04995_amd/costmodel.py).  Not from the paper: it
+ * proposes candidates to the paper's auto-tuner (Section "Auto-tuning"),
+ * which measures them (GIRIH_TUNE_MODEL).
+ *
+ * Network: n_in inputs -> n_layers hidden layers of n_hidden units, each
+ * z = W a + b followed by ReLU -> one linear output.  Parameters: one flat FP32
+ * DEVICE array, layer by layer (first hidden layer first, output layer last):
+ * W (fan_out x fan_in, row-major) then b (fan_out).  Inputs x: n x n_in,
+ * row-major, device.  All buffers are caller-owned device memory; work is a
+ * scratch array of at least girih_mlp_work_count floats.  Sums run in a fixed
+ * order.  Asynchronous on hip_stream.  Errors: GIRIH_E_INVALID for null
+ * pointers, sizes out of range (n_in, n_hidden <= 4096, 1 <= n_layers <= 16,
+ * n >= 1) or a short work array; GIRIH_E_HIP for a failed launch. */
+int girih_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_layers, int64_t* count);
+int girih_mlp_work_count(int32_t n_in, int32_t n_hidden, int32_t n_layers, int32_t n, int64_t* count);
+/* y[i] = network(x[i]) for i < n (y: n floats, device). */
+int girih_mlp_forward(const float* params, int32_t n_in, int32_t n_hidden, int32_t n_layers, const float* x,
+                      int32_t n, float* y, float* work, int64_t work_len, void* hip_stream);
+/* loss = (1/n) sum_i (network(x[i]) - target[i])^2 (one float, device) and its
+ * gradient with respect to every parameter (grad: param_count floats, device),
+ * by back-propagation. */
+int girih_mlp_loss_grad(const float* params, int32_t n_in, int32_t n_hidden, int32_t n_layers, const float* x,
+                        const float* target, int32_t n, float* loss, float* grad, float* work, int64_t work_len,
+                        void* hip_stream);
+/* One Adam step (Kingma and Ba) on count parameters: m and v are the first and
+ * second moment arrays (device, zero before step 1), step >= 1:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+int girih_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t count, float lr, float beta1,
+                   float beta2, float eps, int32_t step, void* hip_stream);
+
 /* Library version string. */
 const char* girih_version(void);
 

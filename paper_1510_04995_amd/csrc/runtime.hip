@@ -348,8 +348,17 @@ struct TuneBufs {
 };
 
 template <typename Real>
-__global__ void tune_fill_kernel(Real* __restrict__ a, int64_t n, Real v, uint32_t seed) {
+__global__ void tune_fill_kernel(Real* __restrict__ a, int64_t n, Real v, uint32_t seed, int64_t px, int64_t py,
+                                 int64_t nx, int64_t ny, int64_t nz, int h, int zero_halo) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (zero_halo) {
+            // the tuner's fields carry a zero Dirichlet halo, like the workloads
+            const int64_t x = i % px, y = (i / px) % py, z = i / (px * py);
+            if (x < h || x >= nx + h || y < h || y >= ny + h || z < h || z >= nz + h) {
+                a[i] = Real(0);
+                continue;
+            }
+        }
         // cheap hash in [0.5, 1.5) * v : keeps values normal and bounded
         uint32_t x = (uint32_t)i * 2654435761u ^ seed;
         x ^= x >> 15;
@@ -373,9 +382,13 @@ int alloc_tune_bufs(girih_plan_s* p, TuneBufs& b, hipStream_t s) {
         void* q = i < 2 ? b.f[i] : b.coef[i - 2];
         const double v = i < 2 ? 1.0 : cw;
         if (p->dtype == GIRIH_F64)
-            hipLaunchKernelGGL(tune_fill_kernel<double>, dim3(4096), dim3(256), 0, s, (double*)q, n, v, 17u * i + 1);
+            hipLaunchKernelGGL(tune_fill_kernel<double>, dim3(4096), dim3(256), 0, s, (double*)q, n, v, 17u * i + 1,
+                               p->grid.pitch_x, p->grid.pitch_y, p->grid.nx, p->grid.ny, p->grid.nz, p->grid.halo,
+                               i < 2 ? 1 : 0);
         else
-            hipLaunchKernelGGL(tune_fill_kernel<float>, dim3(4096), dim3(256), 0, s, (float*)q, n, (float)v, 17u * i + 1);
+            hipLaunchKernelGGL(tune_fill_kernel<float>, dim3(4096), dim3(256), 0, s, (float*)q, n, (float)v, 17u * i + 1,
+                               p->grid.pitch_x, p->grid.pitch_y, p->grid.nx, p->grid.ny, p->grid.nz, p->grid.halo,
+                               i < 2 ? 1 : 0);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(s));

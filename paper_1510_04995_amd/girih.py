@@ -82,6 +82,19 @@ SIGNATURES = {
     "girih_error_norms": (ctypes.c_int, [ctypes.POINTER(GirihGrid), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "girih_version": (ctypes.c_char_p, []),
+    "girih_mlp_param_count": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int64)]),
+    "girih_mlp_work_count": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    "girih_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p]),
+    "girih_mlp_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "girih_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_int32, ctypes.c_void_p]),
 }
 
 
@@ -217,3 +230,34 @@ def girih_error_norms(grid, dtype_a, a_ptr, dtype_b, b_ptr, stream_ptr):
 
 def girih_version():
     return _lib().girih_version().decode()
+
+
+def _vp(x):
+    return ctypes.c_void_p(int(x)) if x else None
+
+
+def girih_mlp_param_count(n_in, n_hidden, n_layers):
+    c = ctypes.c_int64(0)
+    _check(_lib().girih_mlp_param_count(n_in, n_hidden, n_layers, ctypes.byref(c)), "girih_mlp_param_count")
+    return c.value
+
+
+def girih_mlp_work_count(n_in, n_hidden, n_layers, n):
+    c = ctypes.c_int64(0)
+    _check(_lib().girih_mlp_work_count(n_in, n_hidden, n_layers, n, ctypes.byref(c)), "girih_mlp_work_count")
+    return c.value
+
+
+def girih_mlp_forward(params, n_in, n_hidden, n_layers, x, n, y, work, work_len, stream):
+    _check(_lib().girih_mlp_forward(_vp(params), n_in, n_hidden, n_layers, _vp(x), n, _vp(y), _vp(work),
+                                    int(work_len), _vp(stream)), "girih_mlp_forward")
+
+
+def girih_mlp_loss_grad(params, n_in, n_hidden, n_layers, x, target, n, loss, grad, work, work_len, stream):
+    _check(_lib().girih_mlp_loss_grad(_vp(params), n_in, n_hidden, n_layers, _vp(x), _vp(target), n, _vp(loss),
+                                      _vp(grad), _vp(work), int(work_len), _vp(stream)), "girih_mlp_loss_grad")
+
+
+def girih_mlp_adam(params, grad, m, v, count, lr, beta1, beta2, eps, step, stream):
+    _check(_lib().girih_mlp_adam(_vp(params), _vp(grad), _vp(m), _vp(v), int(count), float(lr), float(beta1),
+                                 float(beta2), float(eps), int(step), _vp(stream)), "girih_mlp_adam")
