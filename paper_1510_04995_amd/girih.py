@@ -101,6 +101,13 @@ SIGNATURES = {
 def _lib():
     global _LIB
     if _LIB is None:
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system's; loading torch first makes the library bind to that one
+        # runtime, so torch's device pointers and streams are valid in it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libgirih.so is not built (run __graft_entry__.build() or "
                                "python paper_1510_04995_amd/build.py)")

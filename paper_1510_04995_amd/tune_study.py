@@ -1,0 +1,115 @@
+"""Evaluation of the learned cost model against the paper's tuner.
+
+  python -m paper_1510_04995_amd.tune_study [--out report.json] [--log train.jsonl]
+
+1. The tuner measures every feasible blocked candidate (exhaustive search) of
+   the training problems: 7-point constant 64^3 (T = 16) and 512^3 (T = 64),
+   25-point constant 512^3 (T = 32), each in FP64 and FP32.  Every measured
+   candidate is one training record (features, GLUP/s).
+2. The cost model is trained on those records (HIP kernels, Adam).
+3. On grids the model has not seen (256 x 512 x 1024), the study compares
+   exhaustive search, the paper's hill-climbing tuner, the model's top-5 and
+   the paper's "largest tile that fits" pick: best measured GLUP/s, number of
+   candidates measured and tuning time.
+
+Prints one progress line per problem and a JSON report at the end.
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import Sweep
+from . import costmodel as C
+
+TRAIN = [("7c", (64, 64, 64), 16), ("7c", (512, 512, 512), 64), ("25c", (512, 512, 512), 32)]
+EVAL = [("7c", "f64"), ("7c", "f32"), ("25c", "f64")]
+EVAL_GRID = (256, 512, 1024)
+EVAL_T = 64
+CONSTS = {"7c": [0.4, 0.1], "25c": [0.2, 0.05, 0.04, 0.03, 0.0133]}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def largest_tile_pick(sw, T):
+    """The paper's capacity rule: the candidate with the largest diamond width,
+    then the widest x tile, that the on-chip budget admits."""
+    table = C.candidate_table(sw, T)
+    best = max(table, key=lambda r: (r[0]["diamond_width"], r[0]["tile_x"] * 1.0, r[0]["threads_x"]))
+    return best[0]
+
+
+def timed_tune(sw, mode, T, budget, cands=None):
+    if cands is not None:
+        sw.set_candidates(cands)
+    n0 = len(sw.tune_log())
+    t0 = time.perf_counter()
+    best, rate = sw.tune(mode, T, budget)
+    return {"glups": rate, "measured": len(sw.tune_log()) - n0, "seconds": time.perf_counter() - t0,
+            "params": {k: best[k] for k in ("diamond_width", "tile_x", "threads_x", "cells_per_lane")}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--log", default=None, help="write the training records as JSON lines")
+    ap.add_argument("--budget", type=float, default=60.0, help="seconds per exhaustive search")
+    args = ap.parse_args()
+
+    X, y, rows = [], [], []
+    for st, n, T in TRAIN:
+        for dt in ("f64", "f32"):
+            sw = Sweep(st, dt, *n, CONSTS[st], "mwd")
+            r = timed_tune(sw, "exhaustive", T, args.budget)
+            Xi, yi = C.records_from_log(sw, T, sw.tune_log())
+            X += Xi
+            y += yi
+            for f, g in zip(Xi, yi):
+                rows.append({"stencil": st, "dtype": dt, "grid": n, "T": T, "features": f, "glups": g})
+            say("train %s %s %s: %d candidates, best %.1f GLUP/s, %.1f s" % (st, dt, n, r["measured"], r["glups"],
+                                                                        r["seconds"]))
+            sw.close()
+    if args.log:
+        with open(args.log, "w") as f:
+            for r in rows:
+                f.write(json.dumps(r) + "\n")
+    model = C.CostModel(seed=0)
+    t0 = time.perf_counter()
+    losses = model.fit(X, y, steps=3000)
+    t_fit = time.perf_counter() - t0
+    pred = model.predict(X)
+    fit_err = float(np.median(np.abs(np.log(pred) - np.log(np.asarray(y)))))
+    say("model: %d records, loss %.4f -> %.4f, median |log error| %.3f, %.1f s" % (len(X), losses[0], losses[-1],
+                                                                                  fit_err, t_fit))
+    report = {"train_records": len(X), "train_loss_first": float(losses[0]), "train_loss_last": float(losses[-1]),
+              "train_median_abs_log_error": fit_err, "train_seconds": t_fit, "eval": []}
+    for st, dt in EVAL:
+        res = {"stencil": st, "dtype": dt, "grid": EVAL_GRID, "T": EVAL_T}
+        sw = Sweep(st, dt, *EVAL_GRID, CONSTS[st], "mwd")
+        res["exhaustive"] = timed_tune(sw, "exhaustive", EVAL_T, args.budget)
+        res["hillclimb"] = timed_tune(sw, "hillclimb", EVAL_T, args.budget)
+        res["model_top5"] = timed_tune(sw, "model", EVAL_T, args.budget, model.propose(sw, EVAL_T, 5))
+        res["largest_tile"] = timed_tune(sw, "model", EVAL_T, args.budget, [largest_tile_pick(sw, EVAL_T)])
+        res["model_vs_exhaustive"] = res["model_top5"]["glups"] / res["exhaustive"]["glups"]
+        say("eval %s %s %s: exhaustive %.1f (%d, %.1f s), hill-climb %.1f (%d), model top-5 %.1f (%d, %.1f s), "
+            "largest tile %.1f -> model/exhaustive %.3f"
+            % (st, dt, EVAL_GRID, res["exhaustive"]["glups"], res["exhaustive"]["measured"],
+               res["exhaustive"]["seconds"], res["hillclimb"]["glups"], res["hillclimb"]["measured"],
+               res["model_top5"]["glups"], res["model_top5"]["measured"], res["model_top5"]["seconds"],
+               res["largest_tile"]["glups"], res["model_vs_exhaustive"]))
+        report["eval"].append(res)
+        sw.close()
+    txt = json.dumps(report)
+    print(txt, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(txt + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
