@@ -1,0 +1,251 @@
+"""Host-side models of the diamond-row kernel's index logic (mwd_row_kernel).
+
+These re-derive, in plain Python, the schedule rules the kernel applies per
+workgroup and wave, and check them over many small configurations:
+
+* stage coverage: every (level, row) a computed cell reads from the stage is
+  provided exactly once (computed slots, input slots, stage duties of rows
+  that compute nothing, out-of-span rows, halo rows), and nothing is staged
+  outside the stage layout;
+* address bounds: every coefficient load, halo load and prefetch load of the
+  kernel's two loop bodies (ramp and steady) touches a plane inside the haloed
+  array, and the steady range contains only steps whose level planes and
+  stored planes lie inside the grid.
+
+They need no GPU; the GPU parity tests check the kernel itself.
+"""
+import pytest
+
+
+def partner(R, H, d):
+    b, e = d // R, d % R
+    b2 = H - 1 - b
+    return b2 * R + e if b2 != b else b * R + (e ^ 1)
+
+
+def stage_coverage_errors(R, DW, ny, T):
+    H = DW // (2 * R); L = 2 * H
+    w = lambda k: R * k if k < H else DW // 2 - R * (k - H)
+    def row_levels(j, y, t_c):
+        if j < 0 or j >= DW or y < 0 or y >= ny: return (1, 0)
+        d = j - DW // 2 if j >= DW // 2 else DW // 2 - 1 - j
+        b = d // R
+        lo, hi = b + 1, L - 1 - b
+        lo = max(lo, H - t_c); hi = min(hi, T - 1 + H - t_c)
+        return (lo, hi) if lo <= hi else (1, 0)
+    def in_layout(k, j):
+        if k < 0 or k > L - 2: return False
+        wk = w(k + 1)
+        return DW // 2 - wk - R <= j < DW // 2 + wk + R
+    n_rows = (T - 1) // H + 2
+    errors = []
+    for r in range(n_rows):
+        t_c = r * H
+        off = DW // 2 if r % 2 else 0
+        nd = (ny + DW // 2 - off + DW - 1) // DW
+        for m in range(nd):
+            c = off + m * DW
+            ybase = c - DW // 2
+            kmax = min(L - 1, T - 1 + H - t_c)
+            provided = {}
+            def prov(k, j, who):
+                if not in_layout(k, j):
+                    errors.append(('out of layout', r, c, k, j, who)); return
+                provided.setdefault((k, j), []).append(who)
+            # waves
+            waves = []
+            for side in (0, 1):
+                for d in range(DW // 2):
+                    pd = partner(R, H, d)
+                    if d < pd:
+                        waves.append((side, d, pd))
+            assert len(waves) == DW // 2, (R, DW)
+            for side, dA, dB in waves:
+                for d in (dA, dB):
+                    j = DW // 2 + d if side == 0 else DW // 2 - 1 - d
+                    y = ybase + j
+                    kf, kl = row_levels(j, y, t_c)
+                    for k in range(max(kf, 1), kl + 1):
+                        if k <= L - 2: prov(k, j, 'comp')
+                    # duties
+                    if 0 <= y < ny:
+                        ks = d // R + 1
+                        kv = kf - 1 if kf <= kl else min(ks - 1, kmax - 1)
+                        ok = lambda k: k >= 0 and t_c - H + k + 1 >= 0 and in_layout(k, j)
+                        if kf <= kl: prov(kv, j, 'vring')
+                        if kf > kl and ok(kv): prov(kv, j, 'pre1')
+                        if ok(kv - 1): prov(kv - 1, j, 'pre2')
+                    # out of span
+                    if d // R == H - 1 and t_c < T:
+                        jo = j + R if side == 0 else j - R
+                        if -R <= ybase + jo < ny + R:
+                            prov(H - 1, jo, 'preo')
+            # halo rows
+            for k in range(L - 1):
+                for j in range(DW // 2 - w(k + 1) - R, DW // 2 + w(k + 1) + R):
+                    y = ybase + j
+                    if -R <= y < 0 or ny <= y < ny + R:
+                        prov(k, j, 'halo')
+            # needs
+            for j in range(DW):
+                y = ybase + j
+                kf, kl = row_levels(j, y, t_c)
+                for k in range(kf, kl + 1):
+                    for jj in range(j - R, j + R + 1):
+                        if (k - 1, jj) not in provided:
+                            errors.append(('missing', r, c, k, j, jj))
+            for key, who in provided.items():
+                if len(who) > 1 and not set(who) <= {'halo', 'preo'}:
+                    errors.append(('double', r, c, key, who))
+    return errors
+
+
+
+def bit_range(lo, hi):
+    lo = max(lo, 0); hi = min(hi, 31)
+    return 0 if lo > hi else (((2 << hi) - 1) & ~((1 << lo) - 1)) & 0xffffffff
+
+def row_levels(R, DW, j, y, ny, t_c, T):
+    H = DW // (2 * R); L = 2 * H
+    if j < 0 or j >= DW or y < 0 or y >= ny: return (1, 0)
+    d = j - DW // 2 if j >= DW // 2 else DW // 2 - 1 - j
+    b = d // R
+    lo, hi = max(b + 1, H - t_c), min(L - 1 - b, T - 1 + H - t_c)
+    return (lo, hi) if lo <= hi else (1, 0)
+
+def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True):
+    H = DW // (2 * R); L = 2 * H; RING = 2 * R; NS = L + 2
+    UNR = RING if RING <= 2 else 1
+    nzs = nz + R * (L - 1)
+    zA = ((R * (L - 1) + UNR - 1) // UNR) * UNR
+    zB = max((nz // UNR) * UNR, zA)
+    steps = []
+    zb = -RING
+    while zb < nzs:
+        if zA <= zb < zB: break
+        steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
+    while zb < zB:
+        steps += [(zb + p, True) for p in range(UNR)]; zb += UNR
+    while zb < nzs:
+        steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
+    bad = []
+    def chk(kind, q, y, info):
+        if not (-R <= q < nz + R) or not (-R <= y < ny + R):
+            bad.append((kind, q, y) + info)
+    waves = []
+    for side in (0, 1):
+        for d in range(DW // 2):
+            pd = partner(R, H, d)
+            if d < pd: waves.append((side, d, pd))
+    n_rows = (T - 1) // H + 2
+    for r in range(n_rows):
+        t_c = r * H
+        off = DW // 2 if r % 2 else 0
+        nd = (ny + DW // 2 - off + DW - 1) // DW
+        for m in range(nd):
+            ybase = off + m * DW - DW // 2
+            for side, dA, dB in waves:
+                jA = DW // 2 + dA if side == 0 else DW // 2 - 1 - dA
+                jB = DW // 2 + dB if side == 0 else DW // 2 - 1 - dB
+                kfA, klA = row_levels(R, DW, jA, ybase + jA, ny, t_c, T)
+                kfB, klB = row_levels(R, DW, jB, ybase + jB, ny, t_c, T)
+                cmpA, cmpB = kfA <= klA, kfB <= klB
+                sB = klA - kfA + 2 if cmpA else 1
+                nB = klB - kfB + 2 if cmpB else 1
+                baseA, baseB = kfA - 1, kfB - 1
+                cm = 0; gos = {}
+                for s in range(NS):
+                    isB = s >= sB; t = s - sB if isB else s
+                    valid = (cmpB and t < nB) if isB else cmpA
+                    k = (baseB if isB else baseA) + t
+                    j = jB if isB else jA
+                    gos[s] = (L - k, ybase + j) if valid else (0, -R)   # (planes above the window's first, row); unused: 0, row -R
+                    if valid and t >= 1: cm |= 1 << s
+                maskA = bit_range(0, sB - 1)
+                for zs, steady in steps:
+                    if not steady and zs >= nzs: continue
+                    zS = 0xffffffff
+                    if not steady:
+                        khz = zs // R if zs >= 0 else -1
+                        klz = (zs - nz) // R + 1 if zs - nz >= 0 else 0
+                        zS = (bit_range(klz - baseA, khz - baseA) & maskA) | (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA & 0xffffffff)
+                    for s in range(1, NS):
+                        zv = (((cm & zS) if fixed else zS) >> s) & 1
+                        dz, y = gos[s]
+                        if ncoef and (steady or zv):
+                            chk('coef', zs - R * L + R * dz, y, (r, m, side, dA, zs, steady, s))
+                        if not steady and not zv and not zh:
+                            isB = s >= sB
+                            k = baseB + (s - sB) if isB else baseA + s
+                            q = zs - R * k
+                            if (((cm >> s) & 1) or not fixed) and -R <= q < nz + R:
+                                chk('halo', q, ybase + (jB if isB else jA), (r, m, zs, s))
+    return bad
+
+
+
+def check_prefetch(R, DW, ny, nz, T, PD=2):
+    """Planes of the prefetch loads (both bodies) stay inside [-R, nz+R)."""
+    H = DW // (2 * R); L = 2 * H; RING = 2 * R; UNR = 2
+    nzs = nz + R * L
+    zA = ((R * L + UNR - 1) // UNR) * UNR
+    zB0 = nz if R >= PD else nz + R - PD
+    zB = max((zB0 // UNR) * UNR, zA)
+    steps = []
+    zb = -RING
+    while zb < nzs:
+        if zA <= zb < zB: break
+        steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
+    while zb < zB:
+        steps += [(zb + p, True) for p in range(UNR)]; zb += UNR
+    while zb < nzs:
+        steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
+    bad = []
+    dzs = set(range(0, L)) | {H}
+    for zs, steady in steps:
+        if not steady and zs >= nzs: continue
+        for dz in dzs:
+            q = zs + PD - R * dz
+            if steady and not (-R <= q < nz + R):
+                bad.append((zs, dz, q))
+        if steady:
+            for k in range(L):
+                if not (0 <= zs - R * k < nz) or not (0 <= zs - R * (k + 1) < nz):
+                    bad.append(('plane', zs, k))
+    return bad
+
+
+
+
+CONFIGS = [(1, (4, 8, 12, 16)), (4, (8, 16, 24))]
+
+
+@pytest.mark.parametrize("R,DW", [(R, d) for R, ds in CONFIGS for d in ds])
+def test_every_stage_read_is_provided_once(R, DW):
+    for ny in list(range(1, 2 * DW + 5)) + [3 * DW + 1]:
+        for T in range(1, 3 * DW // R + 3):
+            e = stage_coverage_errors(R, DW, ny, T)
+            assert not e, (R, DW, ny, T, e[:3])
+
+
+@pytest.mark.parametrize("R,DW", [(R, d) for R, ds in CONFIGS for d in ds if d <= 16])
+def test_loads_stay_inside_the_haloed_arrays(R, DW):
+    for ny in (1, 3, 7, 2 * DW + 1):
+        for nz in (1, 3, 9, 14):
+            for T in (1, 3, 7):
+                for zh in (True, False):
+                    e = load_bound_errors(R, DW, 8, ny, nz, T, 1, zh)
+                    assert not e, (R, DW, ny, nz, T, zh, e[:2])
+
+
+def test_the_earlier_z_mask_is_caught():
+    # the mask of an earlier build also covered unused slots: the model flags it
+    assert load_bound_errors(1, 8, 129, 30, 14, 3, 7, True, fixed=False)
+    assert not load_bound_errors(1, 8, 129, 30, 14, 3, 7, True, fixed=True)
+
+
+@pytest.mark.parametrize("R,DW", [(R, d) for R, ds in CONFIGS for d in ds])
+def test_prefetch_planes_and_steady_range(R, DW):
+    for nz in range(1, 40):
+        e = check_prefetch(R, DW, 7, nz, 5)
+        assert not e, (R, DW, nz, e[:3])
