@@ -7,9 +7,9 @@
 
 namespace girih {
 
-template <class S, typename Real, int DW, int VX, int WX>
+template <class S, typename Real, int DW, int VX, int WX, int NSV>
 hipError_t launch_mwd(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
-    hipLaunchKernelGGL((mwd_row_kernel<S, Real, DW, VX, WX>), grid, block, 0, stream,
+    hipLaunchKernelGGL((mwd_row_kernel<S, Real, DW, VX, WX, NSV>), grid, block, 0, stream,
                        *static_cast<const MwdArgs<Real>*>(args));
     return hipGetLastError();
 }
@@ -21,17 +21,26 @@ hipError_t launch_naive(const void* args, dim3 grid, dim3 block, hipStream_t str
     return hipGetLastError();
 }
 
+// A diamond shape registers its full kernel and, where it is smaller, the
+// kernel with H + 3 slots per wave: enough for the first diamond row (levels
+// below H lie before t = 0) and for the last one (levels from H on lie at or
+// after T).
 template <class S, typename Real, int DW, int VX, int WX>
 void add_mwd(std::vector<KernelEntry>& t, int st, int dt) {
     using K = MwdKernel<S, Real, DW, VX, WX>;
-    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX,
-                            reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX>),
-                            &launch_mwd<S, Real, DW, VX, WX>});
+    constexpr int H = K::H, L = K::L;
+    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0,
+                            reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0>),
+                            &launch_mwd<S, Real, DW, VX, WX, 0>});
+    if constexpr (H + 3 < L + 2)
+        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3,
+                                reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3>),
+                                &launch_mwd<S, Real, DW, VX, WX, H + 3>});
 }
 
 template <class S, typename Real>
 void add_naive(std::vector<KernelEntry>& t, int st, int dt) {
-    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0,
+    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0,
                             reinterpret_cast<const void*>(&naive_step_kernel<S, Real>),
                             &launch_naive<S, Real>});
 }
@@ -51,6 +60,7 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         // (diamond width, cells per lane, waves along x)
         add_mwd<S, Real, 4, 2, 2>(t, st, dt);
         add_mwd<S, Real, 8, 1, 2>(t, st, dt);
+        add_mwd<S, Real, 8, 1, 3>(t, st, dt);
         add_mwd<S, Real, 8, 1, 4>(t, st, dt);
         add_mwd<S, Real, 8, 2, 1>(t, st, dt);
         add_mwd<S, Real, 8, 2, 2>(t, st, dt);

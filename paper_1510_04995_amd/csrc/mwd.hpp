@@ -282,18 +282,27 @@ enum : int {
 // steady one, for steps at which the plane of every level lies inside the
 // grid: it computes every slot without tests (unused slots compute values
 // nobody reads) and keeps scalar work per step to a few tests.
-template <class S, typename Real, int DW, int VX, int WX>
+//
+// NSV (0 = L + 2) bounds the slot list: rows whose levels the start or the end
+// of the run clips hold fewer slots per wave, and a kernel with fewer slots
+// does proportionally less work per step.  The host launches such a kernel
+// only for rows whose every wave fits (mwd_slots_needed).
+template <class S, typename Real, int DW, int VX, int WX, int NSV>
 __global__ void __launch_bounds__(64 * (DW / 2) * WX)
 mwd_row_kernel(MwdArgs<Real> a) {
     using KK = MwdKernel<S, Real, DW, VX, WX>;
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
-    constexpr int NS = L + 2;
-    // steps unrolled per loop iteration: two (the ring phases for R = 1, the
-    // two stage buffers, and the two sets of prefetch registers)
+    constexpr int NS = NSV > 0 ? NSV : L + 2;
+    static_assert(NS >= 3 && NS <= L + 2, "slot count");
+    // steps unrolled per loop iteration: two (the ring phases for R = 1 and
+    // the two stage buffers)
     constexpr int UNR = 2;
-    // HBM inputs are loaded PD = 2 steps before the step that uses them
-    constexpr int PD = 2;
+    // HBM inputs are loaded PD steps before the step that uses them, into
+    // one of PD register sets
+    constexpr int PD = 1;
+    // a slot's x/y neighbours are read from the stage LDEP slots ahead
+    constexpr int LDEP = 1;
     constexpr int SB = (int)sizeof(Real);
     static_assert(NS <= 32, "slot masks are 32-bit");
     __shared__ Real stage[KK::LDS_ROWS * XLP];
@@ -549,11 +558,11 @@ mwd_row_kernel(MwdArgs<Real> a) {
         // Prefetch registers, one set per step parity.  qA/qB: the input level
         // kv of a row (its input ring);
         // p2: duty level kv-1; po: the out-of-span row.
-        Real qA[2][VX], qB[2][VX], p2A[2][VX], p2B[2][VX], poA[2][VX], poB[2][VX];
+        Real qA[PD][VX], qB[PD][VX], p2A[PD][VX], p2B[PD][VX], poA[PD][VX], poB[PD][VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
 #pragma unroll
-            for (int c = 0; c < 2; ++c) qA[c][v] = qB[c][v] = p2A[c][v] = p2B[c][v] = poA[c][v] = poB[c][v] = Real(0);
+            for (int c = 0; c < PD; ++c) qA[c][v] = qB[c][v] = p2A[c][v] = p2B[c][v] = poA[c][v] = poB[c][v] = Real(0);
 #pragma unroll
             for (int m = 0; m < RING; ++m) {
 #pragma unroll
@@ -578,24 +587,33 @@ mwd_row_kernel(MwdArgs<Real> a) {
             }
             Real vcA[VX], vcB[VX];
 #pragma unroll
-            for (int v = 0; v < VX; ++v) { vcA[v] = qA[ph & 1][v]; vcB[v] = qB[ph & 1][v]; }
+            for (int v = 0; v < VX; ++v) { vcA[v] = qA[ph % PD][v]; vcB[v] = qB[ph % PD][v]; }
             // ---- A: stage every plane the levels read this step ------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
                 // every slot (unused ones into the spare rows); the duty rows are
-                // written after them
-                static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
-                    constexpr int s = decltype(sc)::value;
+                // written after them.  Only workgroups at the x edge hold halo
+                // lanes, so only they pay for the select.
+                auto stage_slots = [&](auto hzc) __attribute__((always_inline)) {
+                    constexpr bool HZ = decltype(hzc)::value;
+                    static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
+                        constexpr int s = decltype(sc)::value;
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) lds(lcs[s] + BOFF + CORNER + 64 * v * SB) = hz[v] ? Real(0) : ring[s][P(R)][v];
-                });
+                        for (int v = 0; v < VX; ++v)
+                            lds(lcs[s] + BOFF + CORNER + 64 * v * SB) = HZ && hz[v] ? Real(0) : ring[s][P(R)][v];
+                    });
+                };
+                if (ZH && (f & F_EDGE_X))
+                    stage_slots(std::true_type{});
+                else
+                    stage_slots(std::false_type{});
                 // loads for step zs + PD into this step's register set (its
                 // values are consumed above or copied to vcA/vcB): plane
                 // zs + PD - R*dz of each stream; planes outside the haloed grid
                 // are skipped (no computing cell reads them; in the steady range
                 // every plane is inside).  A duty register is staged before its
                 // next load is issued.
-                prefetch(zs, STEADY, qA[ph & 1], qB[ph & 1], p2A[ph & 1], p2B[ph & 1], poA[ph & 1], poB[ph & 1],
+                prefetch(zs, STEADY, qA[ph % PD], qB[ph % PD], p2A[ph % PD], p2B[ph % PD], poA[ph % PD], poB[ph % PD],
                          [&](uint32_t la, const Real (&src)[VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
                 // non-zero halo, edge workgroups only: fixed values in halo columns
                 // of computed rows, and halo rows (latency exposed)
@@ -659,7 +677,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 // x/y neighbours of a slot, read from the stage one slot ahead
                 // of its use (a one-deep software pipeline: deeper prefetching
                 // would hold too many registers)
-                Real nb[2][4 * R][VX];
+                Real nb[LDEP + 1][4 * R][VX];
                 auto load_nb = [&](auto tc) __attribute__((always_inline)) {
                     constexpr int t = decltype(tc)::value;
                     const uint32_t lb = lcs[t - 1] + BOFF;     // corner of (level - 1, row)
@@ -668,14 +686,14 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         const uint32_t c0 = lb + 64 * v * SB + CORNER;
 #pragma unroll
                         for (int r = 1; r <= R; ++r) {
-                            nb[t & 1][r - 1][v] = lds(c0 + r * SB);
-                            nb[t & 1][R + r - 1][v] = lds(c0 - r * SB);
-                            nb[t & 1][2 * R + r - 1][v] = lds(c0 + r * XLP * SB);
-                            nb[t & 1][3 * R + r - 1][v] = lds(c0 - r * XLP * SB);
+                            nb[t % (LDEP + 1)][r - 1][v] = lds(c0 + r * SB);
+                            nb[t % (LDEP + 1)][R + r - 1][v] = lds(c0 - r * SB);
+                            nb[t % (LDEP + 1)][2 * R + r - 1][v] = lds(c0 + r * XLP * SB);
+                            nb[t % (LDEP + 1)][3 * R + r - 1][v] = lds(c0 - r * XLP * SB);
                         }
                     }
                 };
-                load_nb(std::integral_constant<int, 1>{});
+                static_for<1, (LDEP + 1 < NS ? LDEP + 1 : NS)>([&](auto tc) __attribute__((always_inline)) { load_nb(tc); });
                 static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
                     constexpr int s = decltype(sc)::value;
                     Real nv[VX];
@@ -687,7 +705,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         // a computed level whose plane lies inside the grid (unused
                         // slots never count: their offsets are not theirs to load)
                         const bool zv = ((cm & zS) >> s) & 1u;
-                        if constexpr (s + 1 < NS) load_nb(std::integral_constant<int, s + 1>{});
+                        if constexpr (s + LDEP < NS) load_nb(std::integral_constant<int, s + LDEP>{});
                         // issue those reads before this slot's arithmetic
                         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -698,10 +716,10 @@ mwd_row_kernel(MwdArgs<Real> a) {
                             for (int r = 1; r <= R; ++r) {
                                 n.zm[r - 1] = ring[s - 1][P(R - r)][v];
                                 n.zp[r - 1] = r == R ? prev[v] : ring[s - 1][P(R + r)][v];
-                                n.xp[r - 1] = nb[s & 1][r - 1][v];
-                                n.xm[r - 1] = nb[s & 1][R + r - 1][v];
-                                n.yp[r - 1] = nb[s & 1][2 * R + r - 1][v];
-                                n.ym[r - 1] = nb[s & 1][3 * R + r - 1][v];
+                                n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][v];
+                                n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][v];
+                                n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][v];
+                                n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][v];
                             }
                             Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
                             if constexpr (S::NCOEF > 0) {
@@ -807,8 +825,10 @@ mwd_row_kernel(MwdArgs<Real> a) {
         const int zB = (zB0 / UNR) * UNR > zA ? (zB0 / UNR) * UNR : zA;
         // first loads: the inputs of steps -RING and -RING + 1
         auto no_stage = [](uint32_t, const Real (&)[VX]) {};
-        prefetch(-RING - PD, false, qA[0], qB[0], p2A[0], p2B[0], poA[0], poB[0], no_stage);
-        prefetch(-RING - PD + 1, false, qA[1], qB[1], p2A[1], p2B[1], poA[1], poB[1], no_stage);
+        static_for<0, PD>([&](auto pc) __attribute__((always_inline)) {
+            constexpr int c = decltype(pc)::value;
+            prefetch(-RING - PD + c, false, qA[c], qB[c], p2A[c], p2B[c], poA[c], poB[c], no_stage);
+        });
         __syncthreads();
         using General = std::integral_constant<bool, false>;
         using Steady = std::integral_constant<bool, true>;

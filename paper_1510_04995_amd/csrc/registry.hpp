@@ -23,6 +23,7 @@ struct KernelEntry {
     int nthreads;    // MWD workgroup size
     int lds_bytes;   // static LDS per workgroup
     int xown_max;    // MWD: largest owned x tile
+    int ns;          // MWD: register slots per wave (0: all L + 2; fewer: rows clipped by the run's time bounds)
     const void* func;
     LaunchFn launch;
 };

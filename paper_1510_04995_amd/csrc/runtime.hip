@@ -98,9 +98,45 @@ size_t grid_bytes(const girih_plan_s* p) {
 
 const KernelEntry* find_mwd(int st, int dt, int dw, int vx, int wx) {
     for (const auto& e : kernel_table())
-        if (e.algo == AL_MWD && e.stencil == st && e.dtype == dt && e.dw == dw && e.vx == vx && e.wx == wx)
+        if (e.algo == AL_MWD && e.stencil == st && e.dtype == dt && e.dw == dw && e.vx == vx && e.wx == wx &&
+            e.ns == 0)
             return &e;
     return nullptr;
+}
+
+// Register slots a wave of the diamond-row kernel needs in the row with time
+// centre t_c of a T-step run: per wave, row A's input level and computed
+// levels, then row B's (one slot for a row without levels).  Rows are paired
+// as the kernel pairs them (half-distance block b with H-1-b); levels are
+// clipped by the run's time bounds only, which bounds the kernel's count,
+// where rows outside the grid hold one slot.
+int mwd_slots_needed(int R, int dw, int64_t t_c, int64_t T) {
+    const int H = dw / (2 * R), L = 2 * H;
+    auto slots = [&](int d) {
+        const int b = d / R;
+        int64_t lo = b + 1, hi = L - 1 - b;
+        lo = std::max<int64_t>(lo, H - t_c);
+        hi = std::min<int64_t>(hi, T - 1 + H - t_c);
+        return lo <= hi ? (int)(hi - lo + 2) : 1;
+    };
+    int need = 0;
+    for (int d = 0; d < dw / 2; ++d) {
+        const int b = d / R, e = d % R, b2 = H - 1 - b;
+        const int pd = b2 != b ? b2 * R + e : b * R + (e ^ 1);
+        if (d < pd) need = std::max(need, slots(d) + slots(pd));
+    }
+    return need;
+}
+
+// The kernel of a plan's diamond shape with the fewest slots that still hold
+// `need`: the full kernel unless a clipped-row kernel suffices.
+const KernelEntry* mwd_kernel_for(const KernelEntry* full, int need) {
+    const KernelEntry* best = full;
+    for (const auto& e : kernel_table())
+        if (e.algo == AL_MWD && e.stencil == full->stencil && e.dtype == full->dtype && e.dw == full->dw &&
+            e.vx == full->vx && e.wx == full->wx && e.ns > 0 && e.ns >= need && (best->ns == 0 || e.ns < best->ns))
+            best = &e;
+    return best;
 }
 
 const KernelEntry* find_naive(int st, int dt) {
@@ -207,8 +243,8 @@ GridDesc desc_of(const girih_plan_s* p) {
 
 // Launch one sweep kernel; with timing on, bracket it with a pair of events
 // on the same stream.
-int timed_launch(girih_plan_s* p, const void* args, dim3 grid, dim3 block, hipStream_t s) {
-    if (!p->timing) return p->kern->launch(args, grid, block, s) == hipSuccess ? GIRIH_OK : GIRIH_E_HIP;
+int timed_launch(girih_plan_s* p, const KernelEntry* k, const void* args, dim3 grid, dim3 block, hipStream_t s) {
+    if (!p->timing) return k->launch(args, grid, block, s) == hipSuccess ? GIRIH_OK : GIRIH_E_HIP;
     const size_t need = 2 * (size_t)(p->n_timed + 1);
     while (p->events.size() < need) {
         hipEvent_t e;
@@ -216,7 +252,7 @@ int timed_launch(girih_plan_s* p, const void* args, dim3 grid, dim3 block, hipSt
         p->events.push_back(e);
     }
     HIPCHK(hipEventRecord(p->events[2 * p->n_timed], s));
-    HIPCHK(p->kern->launch(args, grid, block, s));
+    HIPCHK(k->launch(args, grid, block, s));
     HIPCHK(hipEventRecord(p->events[2 * p->n_timed + 1], s));
     ++p->n_timed;
     return GIRIH_OK;
@@ -235,7 +271,7 @@ int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs,
     for (int64_t t = 0; t < T; ++t) {
         a.V = b[t & 1];
         a.U = b[(t + 1) & 1];
-        const int rc = timed_launch(p, &a, grid, block, s);
+        const int rc = timed_launch(p, p->kern, &a, grid, block, s);
         if (rc) return rc;
     }
     return GIRIH_OK;
@@ -311,7 +347,8 @@ int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, i
         a.c_first = off;
         const int64_t n_diamonds = (ny + dw / 2 - off + dw - 1) / dw;
         const dim3 grid((unsigned)p->n_xchunks, (unsigned)n_diamonds);
-        rc = timed_launch(p, &a, grid, block, s);
+        const KernelEntry* k = mwd_kernel_for(p->kern, mwd_slots_needed(p->R, dw, a.t_c, T));
+        rc = timed_launch(p, k, &a, grid, block, s);
         if (rc) return rc;
         in_user = !in_user;
     }
@@ -445,7 +482,7 @@ int measure(girih_plan_s* p, TuneBufs& b, hipStream_t s, double max_seconds, gir
 std::vector<girih_params> mwd_candidates(const girih_plan_s* p) {
     std::vector<girih_params> out;
     for (const auto& e : kernel_table()) {
-        if (e.algo != AL_MWD || e.stencil != p->stencil || e.dtype != p->dtype) continue;
+        if (e.algo != AL_MWD || e.stencil != p->stencil || e.dtype != p->dtype || e.ns != 0) continue;
         if (e.xown_max < 8) continue;
         // x tiles: the widest, and the widths that split nx into 1-3 more chunks
         std::set<int64_t> tiles;

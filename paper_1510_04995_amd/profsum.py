@@ -43,7 +43,18 @@ def stats(csv_path, bench_path, out_path, command):
         short = name.split("(")[0][:90]
         lines.append("| %s | %s | %.3f | %.2f | %.1f |" % (short, r["Calls"], float(r["TotalDurationNs"]) * 1e-6,
                                                           float(r["AverageNs"]) * 1e-3, float(r["Percentage"])))
+    # the plan's diamond-row kernels (full and clipped-row slot counts) together:
+    # bench.py's per-launch average covers all of them
+    q = b["config"]["params"]
+    key = "%s, %d, %d, %d," % ("double" if b["dtype"] == "f64" else "float", q["diamond_width"],
+                               q["cells_per_lane"], q["threads_x"] // 64)
+    mine = [r for r in rows if ROW_KERNEL in r["Name"] and key in r["Name"]]
+    calls = sum(int(r["Calls"]) for r in mine)
+    tot_ns = sum(float(r["TotalDurationNs"]) for r in mine)
     rl = b["roofline"]
+    if calls:
+        lines += ["", "Plan's diamond-row kernels together (%d variants): %d calls, average %.2f us" %
+                  (len(mine), calls, tot_ns / calls * 1e-3)]
     lines += ["", "bench.py (same run, HIP events on the launch stream): %d launches, average %.4f ms; "
               "value %.2f GLUP/s" % (rl["launches"], rl["avg_launch_ms"], b["value"])]
     with open(out_path, "w") as f:

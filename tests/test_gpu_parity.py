@@ -64,10 +64,13 @@ def test_naive_block_shapes():
 MWD_CASES = [
     ("7c", "f64", 4, 2, 2, 0, (300, 23, 17), [1, 2, 3, 5, 8]),
     ("7c", "f64", 8, 1, 2, 0, (150, 45, 19), [1, 4, 5, 9, 13]),
+    ("7c", "f64", 8, 1, 3, 0, (400, 45, 19), [5, 9]),
+    ("7c", "f32", 8, 1, 3, 100, (400, 33, 15), [4]),
     ("7c", "f64", 8, 1, 4, 40, (150, 45, 19), [7]),
     ("7c", "f64", 8, 2, 1, 0, (150, 45, 19), [4, 9]),
     ("7c", "f64", 8, 2, 2, 0, (300, 33, 15), [5, 12]),
     ("7c", "f64", 12, 1, 2, 0, (131, 50, 12), [6, 7, 16]),
+    ("7c", "f64", 12, 1, 2, 40, (131, 50, 12), [7]),
     ("7c", "f64", 12, 2, 1, 0, (200, 40, 11), [9, 16]),
     ("7c", "f64", 16, 1, 1, 0, (70, 70, 9), [3, 8, 17]),
     ("7c", "f32", 16, 1, 2, 0, (200, 40, 11), [9, 16]),

@@ -10,7 +10,11 @@ workgroup and wave, and check them over many small configurations:
 * address bounds: every coefficient load, halo load and prefetch load of the
   kernel's two loop bodies (ramp and steady) touches a plane inside the haloed
   array, and the steady range contains only steps whose level planes and
-  stored planes lie inside the grid.
+  stored planes lie inside the grid;
+* slot counts: the count the host uses to pick a kernel with fewer register
+  slots per wave bounds what every wave of every diamond of the row holds,
+  and the first and last rows of a run fit the H + 3 slots of the clipped-row
+  kernel.
 
 They need no GPU; the GPU parity tests check the kernel itself.
 """
@@ -184,7 +188,7 @@ def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True):
 
 
 
-def check_prefetch(R, DW, ny, nz, T, PD=2):
+def check_prefetch(R, DW, ny, nz, T, PD=1):
     """Planes of the prefetch loads (both bodies) stay inside [-R, nz+R)."""
     H = DW // (2 * R); L = 2 * H; RING = 2 * R; UNR = 2
     nzs = nz + R * L
@@ -249,3 +253,41 @@ def test_prefetch_planes_and_steady_range(R, DW):
     for nz in range(1, 40):
         e = check_prefetch(R, DW, 7, nz, 5)
         assert not e, (R, DW, nz, e[:3])
+
+
+def slots_needed(R, DW, t_c, T):
+    """The host's slot count for a row (time clipping only, as the runtime)."""
+    H = DW // (2 * R); L = 2 * H
+    def slots(d):
+        b = d // R
+        lo, hi = max(b + 1, H - t_c), min(L - 1 - b, T - 1 + H - t_c)
+        return hi - lo + 2 if lo <= hi else 1
+    return max(slots(d) + slots(partner(R, H, d)) for d in range(DW // 2) if d < partner(R, H, d))
+
+
+@pytest.mark.parametrize("R,DW", [(R, d) for R, ds in CONFIGS for d in ds])
+def test_clipped_row_slot_counts(R, DW):
+    H = DW // (2 * R); L = 2 * H
+    waves = [(side, d, partner(R, H, d)) for side in (0, 1) for d in range(DW // 2) if d < partner(R, H, d)]
+    for ny in (1, 5, 2 * DW + 3):
+        for T in range(1, 4 * H + 4):
+            n_rows = (T - 1) // H + 2
+            for r in range(n_rows):
+                t_c = r * H
+                off = DW // 2 if r % 2 else 0
+                nd = (ny + DW // 2 - off + DW - 1) // DW
+                need = 0
+                for m in range(nd):
+                    ybase = off + m * DW - DW // 2
+                    for side, dA, dB in waves:
+                        jA = DW // 2 + dA if side == 0 else DW // 2 - 1 - dA
+                        jB = DW // 2 + dB if side == 0 else DW // 2 - 1 - dB
+                        kfA, klA = row_levels(R, DW, jA, ybase + jA, ny, t_c, T)
+                        kfB, klB = row_levels(R, DW, jB, ybase + jB, ny, t_c, T)
+                        nA = klA - kfA + 2 if kfA <= klA else 1
+                        nB = klB - kfB + 2 if kfB <= klB else 1
+                        need = max(need, nA + nB)
+                bound = slots_needed(R, DW, t_c, T)
+                assert need <= bound <= L + 2, (R, DW, ny, T, r, need, bound)
+                if r == 0 or r == n_rows - 1:
+                    assert bound <= H + 3, (R, DW, T, r, bound)
