@@ -8,6 +8,11 @@
       (FETCH_SIZE, WRITE_SIZE: KiB per dispatch), each scaled by what the same
       counter reads for a device-to-device copy of copy_mib MiB in the same run.
 
+  python -m paper_1510_04995_amd.profsum core <pass_a.csv> <pass_b.csv> <bench.json> <out.md> <command...>
+      in-core utilisation of the diamond-row kernel from two SQ counter runs:
+      VALU busy, FP64 rate, LDS busy and bytes, against the CU count, clock
+      and peaks of the chip.
+
 <bench.json> is the JSON line bench.py printed in the profiled run (its plan
 parameters and kernel source hash are recorded with the numbers).
 """
@@ -17,6 +22,11 @@ import sys
 
 ROW_KERNEL = "mwd_row_kernel"
 COPY_KERNEL = "copyBuffer"
+# MI355X: 256 CUs of 4 SIMDs in 8 XCDs; FP64 vector peak 78.6 TFLOP/s; LDS
+# 128 bytes per clock per CU
+N_CU, N_SIMD, N_XCD = 256, 1024, 8
+FP64_PEAK_TFLOPS = 78.6
+LDS_BYTES_PER_CLK = 128
 
 
 def _bench_line(path):
@@ -102,9 +112,74 @@ def traffic(fetch_csv, write_csv, bench_path, copy_mib, out_path, command):
         f.write("\n")
 
 
+def _row_kernel_means(path, key):
+    """{counter: mean over the plan's diamond-row dispatches of the per-dispatch sum}."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if ROW_KERNEL not in r["Kernel_Name"] or key not in r["Kernel_Name"]:
+            continue
+        k = (r["Counter_Name"], int(r["Dispatch_Id"]))
+        per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
+        per[("_ns", int(r["Dispatch_Id"]))] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    out = {}
+    for (c, _), v in per.items():
+        out.setdefault(c, []).append(v)
+    return {c: sum(v) / len(v) for c, v in out.items()}
+
+
+def core(path_a, path_b, bench_path, out_path, command):
+    b = _bench_line(bench_path)
+    q = b["config"]["params"]
+    key = "%s, %d, %d, %d," % ("double" if b["dtype"] == "f64" else "float", q["diamond_width"],
+                               q["cells_per_lane"], q["threads_x"] // 64)
+    m = _row_kernel_means(path_a, key)
+    m.update({k: v for k, v in _row_kernel_means(path_b, key).items() if k not in m})
+    cyc = m["GRBM_GUI_ACTIVE"] / N_XCD              # kernel cycles (the counter sums the XCDs)
+    ns = m["_ns"]
+    clock_ghz = cyc / ns
+    simd_cycles = N_SIMD * cyc
+    valu_busy = 4.0 * m["SQ_ACTIVE_INST_VALU"] / simd_cycles   # a wave64 VALU instruction: 4 cycles of a SIMD
+    fp64_flops = 64.0 * (m["SQ_INSTS_VALU_ADD_F64"] + m["SQ_INSTS_VALU_MUL_F64"])
+    fp64_tflops = fp64_flops / ns * 1e-3
+    lds_busy = m["SQ_LDS_IDX_ACTIVE"] / (N_CU * cyc)
+    lds_bytes = 64.0 * (m["SQ_INSTS_LDS_LOAD_BANDWIDTH"] + m["SQ_INSTS_LDS_STORE_BANDWIDTH"])
+    lds_bw = lds_bytes / (N_CU * cyc)
+    waves = m["SQ_WAVES"]
+    rl = b["roofline"]
+    rows = [("kernel duration (counter run, mean over the plan's row launches)", "%.3f ms" % (ns * 1e-6)),
+            ("shader clock (GRBM_GUI_ACTIVE / duration)", "%.2f GHz" % clock_ghz),
+            ("waves per launch", "%.0f" % waves),
+            ("VALU busy, all 1024 SIMDs (4 x SQ_ACTIVE_INST_VALU / SIMD cycles)", "%.1f %%" % (100 * valu_busy)),
+            ("VALU instructions per wave", "%.0f" % (m["SQ_INSTS_VALU"] / waves)),
+            ("FP64 add+mul instructions / VALU instructions", "%.1f %%" % (
+                100 * (m["SQ_INSTS_VALU_ADD_F64"] + m["SQ_INSTS_VALU_MUL_F64"]) / m["SQ_INSTS_VALU"])),
+            ("FP64 rate (64 x add+mul instructions / duration)", "%.2f TFLOP/s = %.1f %% of %.1f" % (
+                fp64_tflops, 100 * fp64_tflops / FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS)),
+            ("LDS busy, all 256 CUs (SQ_LDS_IDX_ACTIVE / CU cycles)", "%.1f %%" % (100 * lds_busy)),
+            ("LDS bytes per CU per clock (64 B x LDS load+store bandwidth units)", "%.1f of %d" % (
+                lds_bw, LDS_BYTES_PER_CLK)),
+            ("LDS bank conflicts (SQ_LDS_BANK_CONFLICT)", "%.0f" % m.get("SQ_LDS_BANK_CONFLICT", 0.0)),
+            ("SALU instructions per wave", "%.0f" % (m["SQ_INSTS_SALU"] / waves)),
+            ("LDS instructions per wave", "%.0f" % (m["SQ_INSTS_LDS"] / waves))]
+    lines = ["# In-core utilisation, diamond-row kernel, %s" % b["config"]["workload"], "",
+             "Command: `%s`" % command, "",
+             "Plan: %s" % json.dumps({k: q[k] for k in ("diamond_width", "tile_x", "threads_x", "cells_per_lane")}),
+             "Kernel source hash: %s" % b["config"]["kernel_source_hash"], "",
+             "Means over the plan's diamond-row launches (both slot-count instances) of two SQ counter runs; "
+             "chip totals: %d CUs, %d SIMDs, %d XCDs." % (N_CU, N_SIMD, N_XCD), "",
+             "| quantity | value |", "|---|---|"]
+    lines += ["| %s | %s |" % r for r in rows]
+    lines += ["", "bench.py (same run): %.2f GLUP/s, %.1f %% of the HBM roofline at %.3f B/LUP (model)" % (
+        b["value"], 100 * rl["frac"], rl["bytes_per_lup_model"])]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
+    elif sys.argv[1] == "core":
+        core(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], " ".join(sys.argv[6:]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], " ".join(sys.argv[7:]))
     else:
