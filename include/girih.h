@@ -81,8 +81,13 @@ typedef struct girih_grid {
  *         threads_y      row pairs = waves along y (filled in: Dw/2);
  *         tile_y, tile_z filled in: Dw and nz;
  *         variant        0 = barrier per wavefront step.
- *  NAIVE: threads_x, threads_y  block shape (x lanes, y rows);
- *         tile_z         z planes each thread marches. */
+ *  NAIVE: variant        0 = x/y neighbours through the caches (any block
+ *                        of at most 256 threads, threads_x a multiple of 64),
+ *                        1 = each plane's x/y neighbourhood staged in an LDS
+ *                        tile (threads_x = 64, threads_y = 4, 8 or 16);
+ *         threads_x, threads_y  block shape (x lanes, y rows);
+ *         tile_z         z planes each thread marches.
+ *         All zero: variant 1 with 64 x 16 threads and 128 planes. */
 typedef struct girih_params {
     int32_t diamond_width;
     int32_t wavefront_depth;

@@ -21,6 +21,13 @@ hipError_t launch_naive(const void* args, dim3 grid, dim3 block, hipStream_t str
     return hipGetLastError();
 }
 
+template <class S, typename Real, int BY>
+hipError_t launch_naive_tile(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
+    hipLaunchKernelGGL((naive_tile_kernel<S, Real, BY>), grid, block, 0, stream,
+                       *static_cast<const NaiveArgs<Real>*>(args));
+    return hipGetLastError();
+}
+
 // A diamond shape registers its full kernel and, where it is smaller, the
 // kernel with H + 3 slots per wave: enough for the first diamond row (levels
 // below H lie before t = 0) and for the last one (levels from H on lie at or
@@ -29,20 +36,31 @@ template <class S, typename Real, int DW, int VX, int WX>
 void add_mwd(std::vector<KernelEntry>& t, int st, int dt) {
     using K = MwdKernel<S, Real, DW, VX, WX>;
     constexpr int H = K::H, L = K::L;
-    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0,
+    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0, 0,
                             reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0>),
                             &launch_mwd<S, Real, DW, VX, WX, 0>});
     if constexpr (H + 3 < L + 2)
-        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3,
+        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3, 0,
                                 reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3>),
                                 &launch_mwd<S, Real, DW, VX, WX, H + 3>});
 }
 
+template <class S, typename Real, int BY>
+void add_naive_tile(std::vector<KernelEntry>& t, int st, int dt) {
+    constexpr int R = S::R;
+    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 64 * BY, (BY + 2 * R) * (64 + 2 * R) * (int)sizeof(Real), 0,
+                            0, 1, reinterpret_cast<const void*>(&naive_tile_kernel<S, Real, BY>),
+                            &launch_naive_tile<S, Real, BY>});
+}
+
 template <class S, typename Real>
 void add_naive(std::vector<KernelEntry>& t, int st, int dt) {
-    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0,
+    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0,
                             reinterpret_cast<const void*>(&naive_step_kernel<S, Real>),
                             &launch_naive<S, Real>});
+    add_naive_tile<S, Real, 4>(t, st, dt);
+    add_naive_tile<S, Real, 8>(t, st, dt);
+    add_naive_tile<S, Real, 16>(t, st, dt);
 }
 
 // Variants per radius and element size.  Each keeps its z-rings in registers

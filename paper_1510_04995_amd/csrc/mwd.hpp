@@ -30,10 +30,10 @@
 //    is chunked for on-chip capacity and parallel slack); all lanes compute
 //    every cell, values outside a level's valid range are never consumed.
 //
-// Register layout: row A may hold any level 1..L-1, row B only levels
-// KB_LO..KB_HI (the band every partner row lives in), both indexed by the
-// level itself, so every ring index and every LDS offset except the row term
-// is a compile-time constant.
+// Register layout: a wave's two rows form one list of register slots (row
+// A's input level and computed levels, then row B's), so every wave runs the
+// same code whatever its rows' level ranges; a slot's ring sits at a
+// compile-time register index, its level and LDS row are per-wave values.
 //
 // Buffers: diamonds of one row are independent, but redundantly computed
 // x-halos read cells that the neighbouring x-chunk of the same diamond may
@@ -113,12 +113,6 @@ struct DiamondShape {
     // levels 0..L-2 (read by the level above) and level L-1, whose 2R rows are
     // staged only to be stored
     static constexpr int STAGE_ROWS = sbase(L);
-    // the band of levels a partner (row B) can hold
-    static constexpr int BMIN = H / 2;
-    static constexpr int KB_LO = BMIN + 1;
-    static constexpr int KB_HI = L - 1 - BMIN;
-    static constexpr int NA = L - 1;
-    static constexpr int NB = KB_HI - KB_LO + 1;
     static_assert(DW % (2 * R) == 0, "diamond width must be a multiple of 2R");
     static_assert(R != 1 || H % 2 == 0, "for R = 1 the diamond width must be a multiple of 4");
     static_assert(R == 1 || R % 2 == 0, "row pairing needs an even radius");

@@ -66,4 +66,79 @@ naive_step_kernel(NaiveArgs<Real> a) {
     }
 }
 
+// Variant 1: the same sweep with the x/y neighbours of each plane taken from
+// an LDS tile.  A block of 64 x BY threads marches z as above; at every plane
+// it stages the (BY + 2R) x (64 + 2R) tile of V around its columns: each
+// thread writes its own centre value from its z-window, and the halo rows and
+// columns come from memory once per block.  With BY rows per block the y
+// halo is read 2R/BY times per update instead of 2R/4 times through the
+// caches, which matters for R = 4.
+template <class S, typename Real, int BY>
+__global__ void __launch_bounds__(64 * BY)
+naive_tile_kernel(NaiveArgs<Real> a) {
+    constexpr int R = S::R, BX = 64, TX = BX + 2 * R, TY = BY + 2 * R;
+    constexpr int NHALO = 2 * R * TX + 2 * R * BY;   // halo cells of the tile
+    __shared__ Real tile[TY][TX];
+    const GridDesc& g = a.g;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int64_t x0 = (int64_t)blockIdx.x * BX, y0 = (int64_t)blockIdx.y * BY;
+    const int64_t x = x0 + tx, y = y0 + ty;
+    const bool mine = x < g.nx && y < g.ny;
+    const int64_t z0 = (int64_t)blockIdx.z * a.z_chunk;
+    int64_t z1 = z0 + a.z_chunk;
+    if (z1 > g.nz) z1 = g.nz;
+    if (z0 >= z1) return;   // uniform across the block
+    const int64_t plane = g.plane();
+    const int64_t px = g.pitch_x;
+    const Real* __restrict__ V = a.V;
+    Real* __restrict__ U = a.U;
+    // clamp into the haloed box: cells past it belong to no computed neighbourhood
+    auto clampx = [&](int64_t v) { return v < -R ? -R : (v > g.nx + R - 1 ? g.nx + R - 1 : v); };
+    auto clampy = [&](int64_t v) { return v < -R ? -R : (v > g.ny + R - 1 ? g.ny + R - 1 : v); };
+    const int64_t xc = clampx(x), yc = clampy(y);
+    Real w[2 * R + 1];
+    int64_t p = g.idx(z0, yc, xc);
+#pragma unroll
+    for (int m = 0; m < 2 * R; ++m) w[m] = V[p + (m - R) * plane];
+    for (int64_t z = z0; z < z1; ++z, p += plane) {
+        w[2 * R] = V[p + R * plane];
+        tile[ty + R][tx + R] = w[R];
+        for (int i = tid; i < NHALO; i += BX * BY) {
+            int r, c;
+            if (i < 2 * R * TX) {            // rows above and below the block
+                const int k = i / TX;
+                r = k < R ? k : BY + k;
+                c = i % TX;
+            } else {                          // columns left and right of it
+                const int k = i - 2 * R * TX;
+                r = R + k / (2 * R);
+                const int cc = k % (2 * R);
+                c = cc < R ? cc : BX + cc;
+            }
+            tile[r][c] = V[g.idx(z, clampy(y0 - R + r), clampx(x0 - R + c))];
+        }
+        __syncthreads();
+        if (mine) {
+            Nbhd<Real, R> n;
+            n.c = w[R];
+#pragma unroll
+            for (int r = 1; r <= R; ++r) {
+                n.xp[r - 1] = tile[ty + R][tx + R + r];
+                n.xm[r - 1] = tile[ty + R][tx + R - r];
+                n.yp[r - 1] = tile[ty + R + r][tx + R];
+                n.ym[r - 1] = tile[ty + R - r][tx + R];
+                n.zp[r - 1] = w[R + r];
+                n.zm[r - 1] = w[R - r];
+            }
+            Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
+#pragma unroll
+            for (int m = 0; m < S::NCOEF; ++m) cf[m] = a.coef.arr[m][p];
+            U[p] = S::apply(n, a.coef.k, cf);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2 * R; ++m) w[m] = w[m + 1];
+    }
+}
+
 }  // namespace girih

@@ -24,6 +24,7 @@ struct KernelEntry {
     int lds_bytes;   // static LDS per workgroup
     int xown_max;    // MWD: largest owned x tile
     int ns;          // MWD: register slots per wave (0: all L + 2; fewer: rows clipped by the run's time bounds)
+    int variant;     // naive: 0 = neighbours through the caches, 1 = plane tiles in LDS (nthreads = 64 x rows)
     const void* func;
     LaunchFn launch;
 };

@@ -139,9 +139,13 @@ const KernelEntry* mwd_kernel_for(const KernelEntry* full, int need) {
     return best;
 }
 
-const KernelEntry* find_naive(int st, int dt) {
+// Naive kernel: variant 0 takes any block shape; variant 1 (plane tiles in
+// LDS) exists for blocks of 64 x `rows` threads.
+const KernelEntry* find_naive(int st, int dt, int variant, int rows) {
     for (const auto& e : kernel_table())
-        if (e.algo == AL_NAIVE && e.stencil == st && e.dtype == dt) return &e;
+        if (e.algo == AL_NAIVE && e.stencil == st && e.dtype == dt && e.variant == variant &&
+            (variant == 0 || e.nthreads == 64 * rows))
+            return &e;
     return nullptr;
 }
 
@@ -200,19 +204,29 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         q.threads_y = dw / 2;
         q.variant = 0;
     } else {
+        // default: plane tiles of 64 x 16 cells marching 128 planes (x/y
+        // halos read once per tile rather than through the caches)
+        const bool dflt = !in || (in->threads_x == 0 && in->threads_y == 0 && in->variant == 0);
+        if (dflt) {
+            q.variant = 1;
+            q.threads_x = 64;
+            q.threads_y = 16;
+            if (q.tile_z == 0) q.tile_z = 128;
+        }
         if (q.threads_x == 0) q.threads_x = 64;
         if (q.threads_y == 0) q.threads_y = 4;
         if (q.tile_z == 0) q.tile_z = 64;
         if (q.threads_x <= 0 || q.threads_y <= 0 || q.tile_z <= 0) return GIRIH_E_INVALID;
-        if (q.threads_x * q.threads_y > 256 || q.threads_x % 64) return GIRIH_E_INVALID;
-        p->kern = find_naive(p->stencil, p->dtype);
+        if (q.variant != 0 && q.variant != 1) return GIRIH_E_UNSUPPORTED;
+        if (q.variant == 0 && (q.threads_x * q.threads_y > 256 || q.threads_x % 64)) return GIRIH_E_INVALID;
+        if (q.variant == 1 && q.threads_x != 64) return GIRIH_E_INVALID;
+        p->kern = find_naive(p->stencil, p->dtype, q.variant, q.threads_y);
         if (!p->kern) return GIRIH_E_UNSUPPORTED;
         q.diamond_width = 0;
         q.wavefront_depth = 0;
         q.tile_x = q.threads_x;
         q.tile_y = q.threads_y;
         q.cells_per_lane = 1;
-        q.variant = 0;
     }
     p->params = q;
     return GIRIH_OK;
@@ -521,6 +535,18 @@ std::vector<girih_params> naive_candidates(const girih_plan_s*) {
                 q.tile_z = c;
                 out.push_back(q);
             }
+    // plane tiles in LDS: 64 x rows threads
+    const int rows[] = {4, 8, 16};
+    const int tz1[] = {64, 128, 256};
+    for (int b : rows)
+        for (int c : tz1) {
+            girih_params q{};
+            q.threads_x = 64;
+            q.threads_y = b;
+            q.tile_z = c;
+            q.variant = 1;
+            out.push_back(q);
+        }
     return out;
 }
 

@@ -59,6 +59,23 @@ def test_naive_block_shapes():
         assert_bitwise(got, ref, "naive %s" % p)
 
 
+@pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v"])
+def test_naive_plane_tiles_bitwise(stencil):
+    """The LDS-tile naive sweep (variant 1) at every compiled tile height, on
+    grids whose x and y are not multiples of the tile and z chunks that do not
+    divide nz, equals the oracle in FP64 and FP32."""
+    n = (70, 37, 23) if stencil.startswith("7") else (135, 41, 19)
+    u0, c, arr = inputs(stencil, *n, seed=5)
+    for dtype in ("f64", "f32"):
+        ref = oracle_run(stencil, u0, c, arr, 3, dtype)
+        for rows, tz in ((4, 7), (8, 64), (16, 5)):
+            p = {"variant": 1, "threads_x": 64, "threads_y": rows, "tile_z": tz}
+            print("naive tiles", stencil, dtype, p, flush=True)
+            got, info = run_gpu(stencil, dtype, u0, c, arr, 3, algo="naive", params=p)
+            assert info["params"]["variant"] == 1
+            assert_bitwise(got, ref, "naive tiles %s %s %s" % (stencil, dtype, p))
+
+
 # (stencil, dtype, Dw, cells per lane, waves along x, tile_x or 0, grid (nx, ny, nz), list of T):
 # every compiled MWD variant at least once, each grid several x chunks wide
 MWD_CASES = [
