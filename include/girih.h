@@ -87,7 +87,10 @@ typedef struct girih_grid {
  *                        tile (threads_x = 64, threads_y = 4, 8 or 16);
  *         threads_x, threads_y  block shape (x lanes, y rows);
  *         tile_z         z planes each thread marches.
- *         All zero: variant 1 with 64 x 16 threads and 128 planes. */
+ *         All zero: variant 1 with 64 x 16 threads and z chunks of up to
+ *         128 planes; for the 7-point constant stencil in FP32 variant 0
+ *         with 64 x 4 threads and up to 64 planes; fewer planes per chunk on
+ *         small grids. */
 typedef struct girih_params {
     int32_t diamond_width;
     int32_t wavefront_depth;

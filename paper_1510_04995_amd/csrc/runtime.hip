@@ -204,14 +204,23 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         q.threads_y = dw / 2;
         q.variant = 0;
     } else {
-        // default: plane tiles of 64 x 16 cells marching 128 planes (x/y
-        // halos read once per tile rather than through the caches)
+        // Defaults (measured on the 512^3, 384^3 and 256x512x1024 workloads):
+        // plane tiles in LDS of 64 x 16 cells marching up to 128 planes; for
+        // the 7-point constant stencil in FP32, whose update is the cheapest,
+        // cached neighbours with 64 x 4 blocks (the tile's two barriers per
+        // plane cost more there than the halo re-reads).  The z chunk keeps
+        // at least two blocks per CU on small grids.
         const bool dflt = !in || (in->threads_x == 0 && in->threads_y == 0 && in->variant == 0);
         if (dflt) {
-            q.variant = 1;
+            const bool cached = p->stencil == GIRIH_7PT_CONST && p->dtype == GIRIH_F32;
             q.threads_x = 64;
-            q.threads_y = 16;
-            if (q.tile_z == 0) q.tile_z = 128;
+            q.threads_y = cached ? 4 : 16;
+            q.variant = cached ? 0 : 1;
+            if (q.tile_z == 0) {
+                const int64_t cols = ((p->grid.nx + 63) / 64) * ((p->grid.ny + q.threads_y - 1) / q.threads_y);
+                const int64_t tz = cols * p->grid.nz / 512;
+                q.tile_z = (int32_t)std::max<int64_t>(8, std::min<int64_t>(cached ? 64 : 128, tz));
+            }
         }
         if (q.threads_x == 0) q.threads_x = 64;
         if (q.threads_y == 0) q.threads_y = 4;

@@ -33,7 +33,7 @@ CASES = [
     ("25c", "f64", (512, 512, 512), 32, "mwd", {"diamond_width": 16, "cells_per_lane": 1, "threads_x": 64}),
 ]
 CONSTS = {"7c": [0.4, 0.1], "25c": [0.2, 0.05, 0.04, 0.03, 0.0133]}
-SWEEP_KERNELS = ("mwd_row_kernel", "naive_step_kernel")
+SWEEP_KERNELS = ("mwd_row_kernel", "naive_step_kernel", "naive_tile_kernel")
 COPY_KERNEL = "copyBuffer"
 
 
