@@ -152,14 +152,14 @@ const KernelEntry* find_naive(int st, int dt, int variant, int rows) {
 // Default MWD shape per radius and element size (diamond width, cells per
 // lane, waves along x); the tuner replaces it per problem.
 void default_mwd(int R, int dtype, int& dw, int& vx, int& wx) {
-    (void)dtype;
     if (R == 1) {
         dw = 12;
         vx = 1;
         wx = 2;
     } else {
+        // FP32 halves the z-ring registers: two cells per lane fit
         dw = 16;
-        vx = 1;
+        vx = dtype == GIRIH_F32 ? 2 : 1;
         wx = 1;
     }
 }
