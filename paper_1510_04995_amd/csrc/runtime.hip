@@ -164,6 +164,27 @@ void default_mwd(int R, int dtype, int& dw, int& vx, int& wx) {
     }
 }
 
+// Default owned x tile: as many x chunks as keep one diamond row's
+// workgroups within one round on the device's CUs (one workgroup per CU),
+// but never a tile wider than the kernel holds nor narrower than half of
+// that (the redundant x-halo grows as the tile shrinks).  More chunks in the
+// same round spread a row's HBM traffic over more CUs.
+int64_t default_x_tile(const girih_plan_s* p, const KernelEntry* k, int dw) {
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0) {
+        (void)hipGetLastError();
+        n_cu = 256;   // MI355X
+    }
+    const int64_t nx = p->grid.nx;
+    const int64_t n_diamonds = (p->grid.ny + dw / 2 + dw - 1) / dw;   // the larger of the two row offsets
+    const int64_t c_min = (nx + k->xown_max - 1) / k->xown_max;
+    const int64_t c_max = std::max<int64_t>(1, n_cu / std::max<int64_t>(1, n_diamonds));
+    const int64_t c_half = (nx + k->xown_max / 2 - 1) / std::max(1, k->xown_max / 2);
+    const int64_t c = std::max(c_min, std::min({c_max, c_half, nx}));
+    return (nx + c - 1) / c;
+}
+
 // Resolve and validate parameters; fills derived fields of the plan.
 int resolve(girih_plan_s* p, const girih_params* in) {
     girih_params q{};
@@ -187,7 +208,7 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         const int64_t win = (int64_t)R * (dw / R + 1) + 1;
         if (win * p->grid.pitch_y * p->grid.pitch_x * (int64_t)elem_bytes(p->dtype) >= (int64_t)1 << 31)
             return GIRIH_E_UNSUPPORTED;
-        int64_t xo = q.tile_x ? q.tile_x : k->xown_max;
+        int64_t xo = q.tile_x ? q.tile_x : default_x_tile(p, k, dw);
         if (xo <= 0) return GIRIH_E_INVALID;
         if (xo > k->xown_max) return GIRIH_E_LDS;
         if (xo > p->grid.nx) xo = std::max<int64_t>(1, p->grid.nx);

@@ -14,7 +14,9 @@
       sweep's HBM roofline ((2 + N_coef) x element bytes per update at 8 TB/s).
 
 The blocked sweep serves the constant-coefficient stencils; the
-variable-coefficient workloads run the naive sweep only.
+variable-coefficient workloads run the naive sweep only.  One more case is
+one GPU's share of the 512^3 7-point problem split in y across two GPUs
+(512 x 256 x 512), the shape a y-slab decomposition gives each device.
 """
 import json
 import sys
@@ -32,7 +34,7 @@ def run(reps):
     import numpy as np
     import torch
     from . import Sweep, error_norms
-    from workloads import WORKLOADS, field_and_coefs
+    from workloads import WORKLOADS, Workload, field_and_coefs
     dev = torch.device("cuda:0")
     # a device-to-device copy of 2 GiB: the HBM rate a streaming kernel reaches
     src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
@@ -49,7 +51,11 @@ def run(reps):
     print(json.dumps({"workload": "device-copy", "bytes": 2 * src.numel() * 8, "seconds": best,
                       "gb_per_s": 2 * src.numel() * 8 / best * 1e-9}), flush=True)
     del src, dst
-    for name, w in WORKLOADS.items():
+    cases = dict(WORKLOADS)
+    base = WORKLOADS["7pt-const-512"]
+    cases["7pt-const-512-yhalf"] = Workload("7pt-const-512-yhalf", "7c", base.nx, base.ny // 2, base.nz, base.T,
+                                            base.const_coefs, ("f64",), note="one GPU's y-slab of 7pt-const-512")
+    for name, w in cases.items():
         h = w.radius
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
         consts = None if c is None else [float(x) for x in c]
