@@ -6,7 +6,7 @@ import json
 
 import pytest
 
-from paper_1510_04995_amd import dw_sweep, profsum, suite
+from paper_1510_04995_amd import dw_sweep, energy, profsum, suite
 
 
 def _write_counters(path, rows):
@@ -123,3 +123,28 @@ def test_suite_table(tmp_path):
     assert "| w | f64 | mwd | 500.0 | 500 | 6.00 | 12, 106, 128, 1 | 0 differ |" in t
     # 25v FP32: (2 + 13) x 4 B per update at 8 TB/s = 133 GLUP/s
     assert "| w | f32 | naive | 60.0 | 133 | 60.00 | - | 1.00e-07 / 2.00e-07 |" in t
+
+
+def test_energy_table(tmp_path):
+    recs = [{"case": "idle", "power_w": 250.0, "samples": 5},
+            {"case": "7c f64 mwd", "stencil": "7c", "dtype": "f64", "algo": "mwd", "grid": [512, 512, 512], "T": 64,
+             "runs": 10, "glups": 500.0, "power_w": 1000.0, "samples": 20, "nj_per_lup": 2.0, "params": {}},
+            {"case": "7c f64 naive", "stencil": "7c", "dtype": "f64", "algo": "naive", "grid": [512, 512, 512],
+             "T": 64, "runs": 10, "glups": 250.0, "power_w": None, "samples": 0, "nj_per_lup": None, "params": {}}]
+    log = tmp_path / "e.log"
+    log.write_text("\n".join(json.dumps(r) for r in recs) + "\n")
+    out = tmp_path / "e.md"
+    energy.summary(str(log), str(out), "cmd")
+    t = out.read_text()
+    assert "Idle power before the runs: 250 W." in t
+    assert "| 7c f64 mwd | 512x512x512, 64 | 500.0 | 1000 | 20 | 2.000 |" in t
+    assert "| 7c f64 naive | 512x512x512, 64 | 250.0 | n/a | 0 | n/a |" in t
+
+
+def test_socket_power_parser(monkeypatch):
+    class R:
+        stdout = json.dumps({"gpu_data": [{"gpu": 0, "power": {"socket_power": {"value": 262, "unit": "W"}}}]})
+    monkeypatch.setattr(energy.subprocess, "run", lambda *a, **k: R())
+    assert energy.socket_power_w() == 262.0
+    R.stdout = "not json"
+    assert energy.socket_power_w() is None
