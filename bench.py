@@ -212,17 +212,20 @@ def main():
         t = time.perf_counter()
         O.sweep(w.stencil, a0, a1, 2, c, None)
         rate = w.nx * w.ny * w.nz * 2 / (time.perf_counter() - t)
-        # about ten seconds of oracle time, at most the whole run
-        t_s = int(max(2, min(w.T, 10.0 * rate / (w.nx * w.ny * w.nz))))
+        # about ten seconds of oracle time: the whole run when it is shorter
+        # (repeated, continuing in time), else part of it
+        t_s = int(max(2, 10.0 * rate / (w.nx * w.ny * w.nz)))
         a0 = u0.copy()
         a1 = u0.copy()
         t = time.perf_counter()
         O.sweep(w.stencil, a0, a1, t_s, c, None)
         dt = time.perf_counter() - t
+        what = ("%d of the %d steps" % (t_s, w.T) if t_s < w.T else
+                "%d steps (the %d-step run %.1f times over)" % (t_s, w.T, t_s / w.T))
         cpu = {"value": round(w.nx * w.ny * w.nz * t_s / dt / 1e9, 4), "unit": "GLUP/s", "cores": O.num_threads(),
                "kind": "oracle",
-               "sample": "%dx%dx%d 7-point constant FP64, %d of the %d steps, plain C sweep (OpenMP over z), %.1f s"
-                         % (w.nx, w.ny, w.nz, t_s, w.T, dt)}
+               "sample": "%dx%dx%d 7-point constant FP64, %s, plain C sweep (OpenMP over z), %.1f s"
+                         % (w.nx, w.ny, w.nz, what, dt)}
 
     out = {
         "metric": "GLUP/s per stencil at 1 GPU + % HBM roofline; blocked vs naive, FP32 vs FP64",
