@@ -1,5 +1,5 @@
 /*
- * Reference sweep for the four Jacobi stencils — TEST INFRASTRUCTURE ONLY.
+ * Reference sweep for the paper's stencils — TEST INFRASTRUCTURE ONLY.
  *
  * This file is the oracle: a plain, slow, obviously correct CPU implementation
  * of what the blocked GPU sweep must reproduce.  Only the test-suite, the smoke
@@ -25,6 +25,11 @@
  *   25v (Listing 4): C00*V + C01*(V[i+1]+V[i-1]) + C02*(V[j+1]+V[j-1])
  *                     + C03*(V[k+1]+V[k-1]) + C04*(x, r=2) + ... + C12*(z, r=4),
  *        accumulated left to right
+ *   25l (Listing 3 as printed, second order in time):
+ *        (2*V - U) + C*(c0*V + c1*S1 + c2*S2 + c3*S3 + c4*S4), where U is the
+ *        value the point holds in the array being overwritten, i.e. time
+ *        level t-1; buf1 therefore holds u^{-1} on entry, not a copy of the
+ *        halo only.  One coefficient array C and five constants.
  *
  * Array layout (Listings 1-4 index U[k][j][i], i fastest): element (k,j,i),
  * with k in [-h, nz+h), j in [-h, ny+h), i in [-h, nx+h), lives at
@@ -38,6 +43,7 @@
 #define ST_7V 1
 #define ST_25C 2
 #define ST_25V 3
+#define ST_25L 4
 
 #define IDX(k, j, i) ((((int64_t)(k) + h) * pitch_y + ((int64_t)(j) + h)) * pitch_x + ((int64_t)(i) + h))
 
@@ -76,6 +82,15 @@ static void step_##SUFFIX(int stencil, int64_t nx, int64_t ny, int64_t nz, int64
                                + V[IDX(k + r, j, i)] + V[IDX(k - r, j, i)];              \
                         u = u + c[r] * s;                                                \
                     }                                                                    \
+                } else if (stencil == ST_25L) {                                          \
+                    REAL b = c[0] * V[p];                                                \
+                    for (int r = 1; r <= 4; r++) {                                       \
+                        REAL s = V[IDX(k, j, i + r)] + V[IDX(k, j, i - r)]               \
+                               + V[IDX(k, j + r, i)] + V[IDX(k, j - r, i)]               \
+                               + V[IDX(k + r, j, i)] + V[IDX(k - r, j, i)];              \
+                        b = b + c[r] * s;                                                \
+                    }                                                                    \
+                    u = 2 * V[p] - U[p] + C[0][p] * b;                                   \
                 } else {                                                                 \
                     u = C[0][p] * V[p];                                                  \
                     for (int r = 1; r <= 4; r++) {                                       \
@@ -96,7 +111,7 @@ int oracle_sweep_##SUFFIX(int stencil, int64_t nx, int64_t ny, int64_t nz, int64
                           int64_t T)                                                     \
 {                                                                                        \
     const int64_t R = (stencil == ST_7C || stencil == ST_7V) ? 1 : 4;                    \
-    if (stencil < 0 || stencil > 3) return -1;                                           \
+    if (stencil < 0 || stencil > 4) return -1;                                           \
     if (nx < 0 || ny < 0 || nz < 0 || T < 0 || h != R) return -1;                        \
     if (pitch_x < nx + 2 * h || pitch_y < ny + 2 * h) return -1;                         \
     REAL *V = buf0, *U = buf1;                                                           \

@@ -17,17 +17,30 @@ paper does not give its initial data; the recipe used here is:
   stencil, C0+..+C6 per point for the 7-point variable stencil,
   C00 + 2*(C01+..+C12) per point for the 25-point variable stencil.  The sum
   is formed in float64, left to right, and each coefficient divided by it;
-* single-precision inputs are the float64 values rounded to nearest.
+* single-precision inputs are the float64 values rounded to nearest;
+* the second-order-in-time 25-point stencil (Listing 3 as printed, "25l")
+  takes the field, then one per-point array C = 0.1 * U[0,1) (a squared
+  Courant number, small enough for the scheme to stay stable), and fixed
+  constants: the eighth-order central second-difference weights
+  c1..c4 = 8/5, -1/5, 8/315, -1/560 and c0 = -6*(c1+c2+c3+c4), so that the
+  bracket is a discrete Laplacian; both buffers start as u^0 (zero initial
+  velocity).
 """
 import math
 from dataclasses import dataclass, field as dc_field
 
 import numpy as np
 
-STENCILS = ("7c", "7v", "25c", "25v")
-RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4}
-N_COEF_ARRAYS = {"7c": 0, "7v": 7, "25c": 0, "25v": 13}
-N_CONST_COEFS = {"7c": 2, "7v": 0, "25c": 5, "25v": 0}
+STENCILS = ("7c", "7v", "25c", "25v", "25l")
+RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4}
+N_COEF_ARRAYS = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1}
+N_CONST_COEFS = {"7c": 2, "7v": 0, "25c": 5, "25v": 0, "25l": 5}
+
+
+def laplacian8_weights():
+    """c0..c4 of the eighth-order 3-D Laplacian used by the 25l workload."""
+    c = [8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0]
+    return np.array([-6.0 * math.fsum(c)] + c, dtype=np.float64)
 
 
 @dataclass(frozen=True)
@@ -63,6 +76,8 @@ WORKLOADS = {
                              note="13 per-point coefficient arrays normalised per point"),
     "7pt-var-256x512x1024": Workload("7pt-var-256x512x1024", "7v", 256, 512, 1024, 64, None, ("f64", "f32"),
                                      note="7 per-point coefficient arrays; unseen by the tuner's training"),
+    "25pt-leapfrog-512": Workload("25pt-leapfrog-512", "25l", 512, 512, 512, 32, None, ("f64", "f32"),
+                                  note="Listing 3 as printed: second order in time, one per-point array"),
 }
 
 
@@ -120,6 +135,9 @@ def field_and_coefs(stencil, nx, ny, nz, seed=0, const_coefs=None, dtype="f64"):
             c = rng.random(5)
             s = math.fsum([c[0]] + [c[r] for r in range(1, 5) for _ in range(6)])
             consts = c / s
+    elif stencil == "25l":
+        consts = laplacian8_weights() if const_coefs is None else np.array(const_coefs, dtype=np.float64)
+        arrays = [_interior(shape, h, 0.1 * rng.random(shape))]
     elif stencil == "7v":
         raw = [rng.random(shape) for _ in range(7)]
         s = raw[0].copy()
