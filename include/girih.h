@@ -43,12 +43,17 @@ extern "C" {
 #define GIRIH_E_NOGPU (-6)       /* no usable gfx950 device */
 
 /* Stencils (paper Listings 1-4; the 25-point constant stencil is the
- * first-order Jacobi form of Listing 3's bracketed term). */
+ * first-order Jacobi form of Listing 3's bracketed term, the leapfrog one is
+ * Listing 3 as printed). */
 typedef enum {
     GIRIH_7PT_CONST = 0,  /* c0, c1 scalars                         */
     GIRIH_7PT_VAR = 1,    /* 7 coefficient arrays C0..C6            */
     GIRIH_25PT_CONST = 2, /* c0..c4 scalars, radius 4               */
-    GIRIH_25PT_VAR = 3    /* 13 coefficient arrays C00..C12, R = 4  */
+    GIRIH_25PT_VAR = 3,   /* 13 coefficient arrays C00..C12, R = 4  */
+    GIRIH_25PT_LEAPFROG = 4 /* c0..c4 scalars and 1 array C, R = 4:
+                             * u^{t+1} = (2u^t - u^{t-1}) + C*(bracket of u^t);
+                             * buf1 holds u^{t-1} = u^{-1} on entry (its
+                             * interior is read), buf0 holds u^0 */
 } girih_stencil;
 
 typedef enum { GIRIH_F64 = 0, GIRIH_F32 = 1 } girih_dtype;
@@ -57,9 +62,9 @@ typedef enum {
     GIRIH_NAIVE = 0, /* T launches of one full-domain Jacobi step              */
     GIRIH_MWD = 1    /* diamond rows: one launch per row of diamond tiles      */
 } girih_algo;
-/* This version provides GIRIH_MWD for the constant-coefficient stencils
- * (GIRIH_7PT_CONST, GIRIH_25PT_CONST); girih_plan returns GIRIH_E_UNSUPPORTED
- * for GIRIH_MWD with a variable-coefficient stencil. */
+/* This version provides GIRIH_MWD for the first-order constant-coefficient
+ * stencils (GIRIH_7PT_CONST, GIRIH_25PT_CONST); girih_plan returns
+ * GIRIH_E_UNSUPPORTED for GIRIH_MWD with the other stencils. */
 
 /* Grid descriptor, in elements. */
 typedef struct girih_grid {

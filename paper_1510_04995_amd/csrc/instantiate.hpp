@@ -75,7 +75,9 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
     // in this version (its coefficient loads are not yet validated on the
     // device): GIRIH_MWD plans for them return GIRIH_E_UNSUPPORTED and the
     // naive sweep serves these stencils.
-    if constexpr (S::NCOEF > 0) {
+    // The second-order-in-time stencil has a naive sweep only: its blocked
+    // form needs a third time level per diamond cell.
+    if constexpr (S::NCOEF > 0 || S::LEAPFROG) {
     } else if constexpr (S::R == 1) {
         // (diamond width, cells per lane, waves along x)
         add_mwd<S, Real, 4, 2, 2>(t, st, dt);

@@ -60,6 +60,7 @@ naive_step_kernel(NaiveArgs<Real> a) {
         Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
 #pragma unroll
         for (int m = 0; m < S::NCOEF; ++m) cf[m] = a.coef.arr[m][p];
+        if constexpr (S::LEAPFROG) n.uo = U[p];   // time level t-1, about to be overwritten
         U[p] = S::apply(n, a.coef.k, cf);
 #pragma unroll
         for (int m = 0; m < 2 * R; ++m) w[m] = w[m + 1];
@@ -133,7 +134,8 @@ naive_tile_kernel(NaiveArgs<Real> a) {
             Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
 #pragma unroll
             for (int m = 0; m < S::NCOEF; ++m) cf[m] = a.coef.arr[m][p];
-            U[p] = S::apply(n, a.coef.k, cf);
+            if constexpr (S::LEAPFROG) n.uo = U[p];   // time level t-1, about to be overwritten
+        U[p] = S::apply(n, a.coef.k, cf);
         }
         __syncthreads();
 #pragma unroll

@@ -48,6 +48,8 @@ const std::vector<KernelEntry>& kernel_table() {
         register_kernels_25c_f32(t);
         register_kernels_25v_f64(t);
         register_kernels_25v_f32(t);
+        register_kernels_25l_f64(t);
+        register_kernels_25l_f32(t);
         return t;
     }();
     return table;
@@ -57,9 +59,13 @@ const std::vector<KernelEntry>& kernel_table() {
 
 namespace {
 
-constexpr int kRadius[4] = {1, 1, 4, 4};
-constexpr int kNCoef[4] = {0, 7, 0, 13};
-constexpr int kNConst[4] = {2, 0, 5, 0};
+constexpr int kRadius[5] = {1, 1, 4, 4, 4};
+constexpr int kNCoef[5] = {0, 7, 0, 13, 1};
+constexpr int kNConst[5] = {2, 0, 5, 0, 5};
+// domain-sized arrays a naive step streams: V and U, the coefficient arrays,
+// and for the second-order-in-time stencil U's old value read before it is
+// overwritten (U is read and written)
+constexpr int kStreams[5] = {2, 9, 2, 15, 4};
 
 struct Tuning {
     std::vector<girih_params> model_cands;
@@ -602,7 +608,7 @@ int girih_plan(girih_plan_t* out, girih_stencil stencil, girih_dtype dtype, cons
                const double* const_coefs, girih_algo algo, const girih_params* params) {
     if (!out) return GIRIH_E_INVALID;
     *out = nullptr;
-    if ((int)stencil < 0 || (int)stencil > 3 || (dtype != GIRIH_F64 && dtype != GIRIH_F32) ||
+    if ((int)stencil < 0 || (int)stencil > 4 || (dtype != GIRIH_F64 && dtype != GIRIH_F32) ||
         (algo != GIRIH_NAIVE && algo != GIRIH_MWD))
         return GIRIH_E_INVALID;
     girih_grid g;
@@ -797,7 +803,7 @@ int girih_plan_info(girih_plan_t p, girih_params* params, int64_t* lds_bytes, do
     if (lds_bytes) *lds_bytes = p->kern ? p->kern->lds_bytes : 0;
     if (model_bytes_per_lup) {
         const double s = (double)elem_bytes(p->dtype);
-        const int ND = 2 + kNCoef[p->stencil];
+        const int ND = kStreams[p->stencil];
         if (p->algo == GIRIH_NAIVE) {
             *model_bytes_per_lup = ND * s;
         } else {

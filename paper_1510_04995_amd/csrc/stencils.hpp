@@ -14,21 +14,28 @@
 //              S_r = x+r + x-r + y+r + y-r + z+r + z-r   (left to right)
 //   Stencil25V (Listing 4): C00*V + C01*(x+1 + x-1) + C02*(y+1 + y-1)
 //              + C03*(z+1 + z-1) + ... + C12*(z+4 + z-4)
+//   Stencil25L (Listing 3 as printed, second order in time):
+//              (2*V - Uold) + C*(c0*V + c1*S1 + c2*S2 + c3*S3 + c4*S4),
+//              Uold = the point's value at time t-1 (the array being written)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace girih {
 
-// Neighbourhood of one point: centre, and for r = 1..R the six axis neighbours.
+// Neighbourhood of one point: centre, and for r = 1..R the six axis
+// neighbours; uo is the point's previous value (second-order-in-time stencils
+// only; LEAPFROG says whether a stencil reads it).
 template <typename Real, int R>
 struct Nbhd {
     Real c;
     Real xp[R], xm[R], yp[R], ym[R], zp[R], zm[R];
+    Real uo;
 };
 
 struct Stencil7C {
     static constexpr int R = 1, NCOEF = 0, NCONST = 2;
+    static constexpr bool LEAPFROG = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 1>& n, const Real* k, const Real*) {
         return ((k[0] * n.c + k[1] * (n.xp[0] + n.xm[0])) + k[1] * (n.yp[0] + n.ym[0]))
@@ -38,6 +45,7 @@ struct Stencil7C {
 
 struct Stencil7V {
     static constexpr int R = 1, NCOEF = 7, NCONST = 0;
+    static constexpr bool LEAPFROG = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 1>& n, const Real*, const Real* C) {
         Real u = C[0] * n.c;
@@ -53,6 +61,7 @@ struct Stencil7V {
 
 struct Stencil25C {
     static constexpr int R = 4, NCOEF = 0, NCONST = 5;
+    static constexpr bool LEAPFROG = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 4>& n, const Real* k, const Real*) {
         Real u = k[0] * n.c;
@@ -71,6 +80,7 @@ struct Stencil25C {
 
 struct Stencil25V {
     static constexpr int R = 4, NCOEF = 13, NCONST = 0;
+    static constexpr bool LEAPFROG = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 4>& n, const Real*, const Real* C) {
         Real u = C[0] * n.c;
@@ -81,6 +91,25 @@ struct Stencil25V {
             u = u + C[3 * r + 3] * (n.zp[r] + n.zm[r]);
         }
         return u;
+    }
+};
+
+struct Stencil25L {
+    static constexpr int R = 4, NCOEF = 1, NCONST = 5;
+    static constexpr bool LEAPFROG = true;
+    template <typename Real>
+    __device__ __forceinline__ static Real apply(const Nbhd<Real, 4>& n, const Real* k, const Real* C) {
+        Real b = k[0] * n.c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Real s = n.xp[r] + n.xm[r];
+            s = s + n.yp[r];
+            s = s + n.ym[r];
+            s = s + n.zp[r];
+            s = s + n.zm[r];
+            b = b + k[r + 1] * s;
+        }
+        return (Real(2) * n.c - n.uo) + C[0] * b;
     }
 };
 

@@ -11,7 +11,9 @@
 
   python -m paper_1510_04995_amd.suite summary <run.log> <out.md> <command...>
       a markdown table of those lines, with each rate next to the naive
-      sweep's HBM roofline ((2 + N_coef) x element bytes per update at 8 TB/s).
+      sweep's HBM roofline (domain-sized streams x element bytes per update at
+      8 TB/s: the field read and written, the coefficient arrays, and for the
+      second-order-in-time stencil the previous level read as well).
 
 The blocked sweep serves the constant-coefficient stencils; the
 variable-coefficient workloads run the naive sweep only.  One more case is
@@ -23,7 +25,7 @@ import sys
 import time
 
 HBM_PEAK_BYTES = 8.0e12
-N_COEF = {"7c": 0, "7v": 7, "25c": 0, "25v": 13}
+STREAMS = {"7c": 2, "7v": 9, "25c": 2, "25v": 15, "25l": 4}
 
 
 def _grid(a, torch, dev):
@@ -60,7 +62,7 @@ def run(reps):
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
         consts = None if c is None else [float(x) for x in c]
         ref = None
-        algos = ("naive", "mwd") if N_COEF[w.stencil] == 0 else ("naive",)
+        algos = ("naive", "mwd") if w.stencil in ("7c", "25c") else ("naive",)
         for dt in w.dtypes:
             npdt = np.float64 if dt == "f64" else np.float32
             g0 = _grid(u0.astype(npdt), torch, dev)
@@ -111,7 +113,8 @@ def summary(run_log, out_path, command):
     lines = ["# Throughput of the study's workloads", "",
              "Command: `%s`" % command, "",
              "GLUP/s = nx*ny*nz*T / best of the timed runs (inputs resident in HBM).  Naive roofline: "
-             "(2 + N_coef) x element bytes per update at 8 TB/s.  Checks against the naive FP64 result: "
+             "domain-sized streams (field read + written, coefficient arrays, previous level for 25l) x element "
+             "bytes per update at 8 TB/s.  Checks against the naive FP64 result: "
              "blocked FP64 elements differing in any bit; FP32 relative L2 / max abs error.", "",
              "| workload | dtype | sweep | GLUP/s | naive roofline | model B/update | plan (Dw, x tile, threads_x, "
              "cells/lane) | check |", "|---|---|---|---|---|---|---|---|"]
@@ -120,7 +123,7 @@ def summary(run_log, out_path, command):
         lines.insert(6, "")
     for r in recs:
         s = 8 if r["dtype"] == "f64" else 4
-        roof = HBM_PEAK_BYTES / ((2 + N_COEF[r["stencil"]]) * s) * 1e-9
+        roof = HBM_PEAK_BYTES / (STREAMS[r["stencil"]] * s) * 1e-9
         q = r["params"]
         plan = "-" if r["algo"] == "naive" else "%d, %d, %d, %d" % (q["diamond_width"], q["tile_x"], q["threads_x"],
                                                                     q["cells_per_lane"])

@@ -25,8 +25,12 @@ def upload(a, pitch_x=None, pitch_y=None, h=None):
 
 
 def run_gpu(stencil, dtype, u0, consts, arrays, T, algo="mwd", params=None, poison=True, pitch=None,
-            return_tensors=False):
-    """Run the library on seeded numpy inputs; returns the unpadded numpy result."""
+            return_tensors=False, prev=None):
+    """Run the library on seeded numpy inputs; returns the unpadded numpy result.
+
+    buf1 starts as a copy of u0 whose interior is NaN (``poison``: the
+    first-order stencils must not read it), except for the second-order-in-time
+    stencil, which reads it as u^{-1}: ``prev`` (default u0)."""
     import paper_1510_04995_amd as P
     torch, dev = torch_dev()
     h = RADIUS[stencil]
@@ -35,9 +39,12 @@ def run_gpu(stencil, dtype, u0, consts, arrays, T, algo="mwd", params=None, pois
     px, py = (pitch or (None, None))
     npdt = np.float64 if dtype == "f64" else np.float32
     b0 = upload(u0.astype(npdt), px, py)
-    b1 = b0.clone()
-    if poison:
-        b1[h:h + nz, h:h + ny, h:h + nx] = float("nan")
+    if stencil == "25l":
+        b1 = upload((u0 if prev is None else prev).astype(npdt), px, py)
+    else:
+        b1 = b0.clone()
+        if poison:
+            b1[h:h + nz, h:h + ny, h:h + nx] = float("nan")
     coefs = [upload(a.astype(npdt), px, py) for a in (arrays or [])]
     sw = P.Sweep(stencil, dtype, nx, ny, nz, None if consts is None else [float(c) for c in consts], algo, params,
                  pitch_x=px or 0, pitch_y=py or 0)
@@ -51,11 +58,11 @@ def run_gpu(stencil, dtype, u0, consts, arrays, T, algo="mwd", params=None, pois
     return res, info
 
 
-def oracle_run(stencil, u0, consts, arrays, T, dtype="f64"):
+def oracle_run(stencil, u0, consts, arrays, T, dtype="f64", prev=None):
     from oracle import sweep as osw
     npdt = np.float64 if dtype == "f64" else np.float32
     b0 = np.ascontiguousarray(u0.astype(npdt))
-    b1 = b0.copy()
+    b1 = b0.copy() if prev is None else np.ascontiguousarray(prev.astype(npdt))
     ar = None if arrays is None else [np.ascontiguousarray(a.astype(npdt)) for a in arrays]
     c = None if consts is None else np.asarray(consts, dtype=npdt)
     idx = osw.sweep(stencil, b0, b1, T, c, ar)

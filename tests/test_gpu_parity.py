@@ -37,7 +37,8 @@ def assert_bitwise(a, b, what):
                              % (what, len(bad), bad[:3].tolist(), a[tuple(bad[0])], b[tuple(bad[0])]))
 
 
-CASES_NAIVE = [("7c", (37, 29, 23), 5), ("7v", (35, 19, 21), 4), ("25c", (45, 37, 29), 3), ("25v", (41, 35, 33), 2)]
+CASES_NAIVE = [("7c", (37, 29, 23), 5), ("7v", (35, 19, 21), 4), ("25c", (45, 37, 29), 3), ("25v", (41, 35, 33), 2),
+               ("25l", (43, 37, 31), 3)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -59,7 +60,7 @@ def test_naive_block_shapes():
         assert_bitwise(got, ref, "naive %s" % p)
 
 
-@pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v"])
+@pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v", "25l"])
 def test_naive_plane_tiles_bitwise(stencil):
     """The LDS-tile naive sweep (variant 1) at every compiled tile height, on
     grids whose x and y are not multiples of the tile and z chunks that do not
@@ -74,6 +75,27 @@ def test_naive_plane_tiles_bitwise(stencil):
             got, info = run_gpu(stencil, dtype, u0, c, arr, 3, algo="naive", params=p)
             assert info["params"]["variant"] == 1
             assert_bitwise(got, ref, "naive tiles %s %s %s" % (stencil, dtype, p))
+
+
+def test_leapfrog_with_initial_velocity_bitwise():
+    """The second-order-in-time stencil reads buf1 as u^{-1}: with u^{-1} != u^0
+    both naive variants follow the oracle bit for bit, in FP64 and FP32, and
+    planning it with the blocked algorithm is refused."""
+    import paper_1510_04995_amd.girih as G
+    n = (69, 33, 27)
+    u0, c, arr = inputs("25l", *n, seed=7)
+    rng = np.random.default_rng(8)
+    prev = u0.copy()
+    prev[4:-4, 4:-4, 4:-4] = rng.random(n[::-1])
+    for dtype in ("f64", "f32"):
+        ref = oracle_run("25l", u0, c, arr, 5, dtype, prev=prev)
+        for p in ({"variant": 0, "threads_x": 64, "threads_y": 4, "tile_z": 9},
+                  {"variant": 1, "threads_x": 64, "threads_y": 8, "tile_z": 16}):
+            got, _ = run_gpu("25l", dtype, u0, c, arr, 5, algo="naive", params=p, prev=prev)
+            assert_bitwise(got, ref, "leapfrog %s %s" % (dtype, p))
+    with pytest.raises(G.GirihError) as e:
+        run_gpu("25l", "f64", u0, c, arr, 1, algo="mwd")
+    assert e.value.code == G.E_UNSUPPORTED
 
 
 # (stencil, dtype, Dw, cells per lane, waves along x, tile_x or 0, grid (nx, ny, nz), list of T):

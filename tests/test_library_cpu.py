@@ -127,3 +127,20 @@ def test_candidates_cover_compiled_variants():
     c = G.girih_candidates(p)
     assert all(q["diamond_width"] % 8 == 0 for q in c) and c
     G.girih_destroy(p)
+
+
+def test_leapfrog_plans():
+    """The second-order-in-time 25-point stencil: naive plans stream four
+    domain-sized arrays (V, U read and written, C); no blocked kernel."""
+    g = G.make_grid(64, 48, 40, 4)
+    c = (-205.0 / 24.0, 1.6, -0.2, 8.0 / 315.0, -1.0 / 560.0)
+    p = G.girih_plan("25l", "f64", g, c, "naive")
+    _, _, bytes_per_lup = G.girih_plan_info(p)
+    assert bytes_per_lup == 32.0
+    G.girih_destroy(p)
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("25l", "f64", g, c, "mwd")
+    assert e.value.code == G.E_UNSUPPORTED
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("25l", "f64", g, None, "naive")          # constants are required
+    assert e.value.code == G.E_INVALID
