@@ -64,7 +64,8 @@ class Workload:
         return self.nx * self.ny * self.nz * self.T
 
 
-# The five workloads of this study.  Sizes are interior points (x fastest).
+# The workloads of this study: the five of its configurations and the
+# second-order 25-point stencil.  Sizes are interior points (x fastest).
 WORKLOADS = {
     "7pt-const-64": Workload("7pt-const-64", "7c", 64, 64, 64, 16, (0.4, 0.1),
                              note="naive GPU sweep vs oracle; fits in cache"),
