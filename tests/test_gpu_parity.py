@@ -215,7 +215,46 @@ def test_mwd_full_size_headline_vs_naive():
                                 [(0, 0, 0), (511, 511, 511), (0, 255, 511), (300, 7, 129), (256, 256, 256)])
 
 
-def check_samples_against_cones(stencil, u0, c, arr, T, out, points):
+@pytest.mark.parametrize("name,dtype", [("25pt-const-512", "f64"), ("25pt-var-384", "f64"),
+                                        ("7pt-var-256x512x1024", "f64"), ("7pt-var-256x512x1024", "f32"),
+                                        ("25pt-leapfrog-512", "f64")])
+def test_full_size_workloads(name, dtype):
+    """The other workloads at their full sizes in their default launch
+    configurations: the blocked sweep (where one exists) equals the naive
+    sweep in every element, and sampled points (corners, faces, interior)
+    equal the oracle evaluated on their light cones."""
+    import paper_1510_04995_amd as P
+    from tests.gpu_util import torch_dev
+    from workloads import WORKLOADS
+    torch, dev = torch_dev()
+    w = WORKLOADS[name]
+    h = w.radius
+    u0, c, arr = inputs(w.stencil, w.nx, w.ny, w.nz, seed=0)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
+    coefs = [] if arr is None else [torch.from_numpy(a.astype(npdt)).to(dev) for a in arr]
+    consts = None if c is None else [float(x) for x in c]
+    algos = ("mwd", "naive") if w.stencil in ("7c", "25c") else ("naive",)
+    res = {}
+    for algo in algos:
+        print("full size", name, dtype, algo, flush=True)
+        sw = P.Sweep(w.stencil, dtype, w.nx, w.ny, w.nz, consts, algo)
+        b0, b1 = g0.clone(), g0.clone()
+        res[algo] = sw.run(b0, b1, w.T, coefs)
+        torch.cuda.synchronize()
+        sw.close()
+    if "mwd" in res:
+        rel, mx, nd = P.error_norms(res["mwd"], res["naive"], h, w.nx, w.ny, w.nz)
+        assert nd == 0 and mx == 0.0
+    out = res["naive"].cpu().numpy()
+    del res, coefs, g0
+    n = (w.nz, w.ny, w.nx)
+    pts = [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (0, n[1] // 2, n[2] - 1), (n[0] // 2, n[1] // 2, n[2] // 2),
+           (n[0] - 1, 3, n[2] // 3)]
+    check_samples_against_cones(w.stencil, u0, c, arr, w.T, out, pts, dtype)
+
+
+def check_samples_against_cones(stencil, u0, c, arr, T, out, points, dtype="f64"):
     """Oracle on the sub-box around each sample that holds its light cone."""
     R = 1 if stencil.startswith("7") else 4
     h = R
@@ -228,7 +267,7 @@ def check_samples_against_cones(stencil, u0, c, arr, T, out, points):
         sl = tuple(slice(lo[d], hi[d] + 2 * h) for d in range(3))
         sub = np.ascontiguousarray(u0[sl])
         sub_arr = None if arr is None else [np.ascontiguousarray(a[sl]) for a in arr]
-        r = oracle_run(stencil, sub, c, sub_arr, T)
+        r = oracle_run(stencil, sub, c, sub_arr, T, dtype)
         q = tuple(p[d] - lo[d] + h for d in range(3))
         full = tuple(p[d] + h for d in range(3))
         assert r[q] == out[full], (p, r[q], out[full])
