@@ -88,7 +88,7 @@ struct MwdArgs {
     const int* zero_halo;  // device flag: 1 if every halo cell of the input is zero
     int64_t T;           // total number of time steps of the run
     int64_t t_c;         // row centre time: row r has t_c = r*H
-    int64_t c_first;     // y centre of the diamond with blockIdx.y == 0
+    int64_t c_first;     // y centre of the row's first diamond
     int32_t x_own;       // x cells stored by one workgroup
 };
 
@@ -309,8 +309,21 @@ mwd_row_kernel(MwdArgs<Real> a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int pw = wave % KK::NPAIRS;              // row pair of this wave
     const int cb = 64 * VX * (wave / KK::NPAIRS);  // first column of this wave's x slice
-    const int ybase = (int)(a.c_first + (int64_t)blockIdx.y * DW) - DW / 2;   // global y of local row 0
-    const int x_own_lo = (int)blockIdx.x * a.x_own;
+    // Workgroups are dealt to the XCDs round-robin in launch order and each
+    // XCD has its own L2.  Renumber so that every XCD takes one contiguous
+    // run of (diamond, x-chunk) tiles: the x chunks of a diamond, whose
+    // redundant halo columns overlap, and neighbouring diamonds, which share
+    // edge rows, then read those cells through the same L2.  (A bijection
+    // for any XCD count; the count only sets the locality.)
+    constexpr uint32_t NXCD = 8;
+    const uint32_t n_tiles = gridDim.x * gridDim.y;
+    const uint32_t launch_id = blockIdx.x + gridDim.x * blockIdx.y;
+    const uint32_t per_xcd = n_tiles / NXCD, extra = n_tiles % NXCD;
+    const uint32_t xcd = launch_id % NXCD, pos = launch_id / NXCD;
+    const uint32_t tile = (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
+    const int chunk = (int)(tile % gridDim.x), diamond = (int)(tile / gridDim.x);
+    const int ybase = (int)(a.c_first + (int64_t)diamond * DW) - DW / 2;   // global y of local row 0
+    const int x_own_lo = chunk * a.x_own;
     const int x_own_hi = x_own_lo + a.x_own < nx ? x_own_lo + a.x_own : nx;
     const int x0 = x_own_lo - KK::HX;              // x of column 0
     const int t_c = (int)a.t_c, T = (int)a.T;

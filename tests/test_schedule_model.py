@@ -291,3 +291,29 @@ def test_clipped_row_slot_counts(R, DW):
                 assert need <= bound <= L + 2, (R, DW, ny, T, r, need, bound)
                 if r == 0 or r == n_rows - 1:
                     assert bound <= H + 3, (R, DW, T, r, bound)
+
+
+def xcd_tile(bx, by, gx, gy, nxcd=8):
+    """The diamond-row kernel's renumbering of its workgroup (bx, by) of a
+    gx x gy launch: XCD-contiguous runs of (diamond, x-chunk) tiles."""
+    nb = gx * gy
+    lid = bx + gx * by
+    q, r = nb // nxcd, nb % nxcd
+    x, pos = lid % nxcd, lid // nxcd
+    t = (x * (q + 1) if x < r else r * (q + 1) + (x - r) * q) + pos
+    return t % gx, t // gx
+
+
+@pytest.mark.parametrize("nxcd", [1, 3, 8])
+def test_workgroup_renumbering_is_a_bijection_with_contiguous_runs(nxcd):
+    for gx in range(1, 9):
+        for gy in range(1, 50):
+            seen = {}
+            for by in range(gy):
+                for bx in range(gx):
+                    seen[xcd_tile(bx, by, gx, gy, nxcd)] = (bx + gx * by) % nxcd
+            assert sorted(seen) == sorted((c, d) for d in range(gy) for c in range(gx))
+            # each XCD's tiles form one run in (diamond, chunk) order
+            order = [seen[(c, d)] for d in range(gy) for c in range(gx)]
+            runs = [order[0]] + [b for a, b in zip(order, order[1:]) if b != a]
+            assert len(runs) == len(set(runs))
