@@ -21,6 +21,7 @@ struct NaiveArgs {
     Real* U;          // time level t+1
     CoefArgs<Real> coef;
     int32_t z_chunk;
+    int32_t xcd_runs;   // variant 1: 1 = renumber blocks into XCD-contiguous runs
 };
 
 template <class S, typename Real>
@@ -82,10 +83,22 @@ naive_tile_kernel(NaiveArgs<Real> a) {
     __shared__ Real tile[TY][TX];
     const GridDesc& g = a.g;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
-    const int64_t x0 = (int64_t)blockIdx.x * BX, y0 = (int64_t)blockIdx.y * BY;
+    // Blocks are dealt to the XCDs round-robin in launch order and each XCD
+    // has its own L2: with xcd_runs, renumber them so that every XCD sweeps
+    // one contiguous run of tiles (x fastest, then y, then z chunks); a tile's
+    // halo rows and columns, read from its neighbours' cells, then come
+    // through the same L2.  (The host turns it off where many coefficient
+    // streams make the launch-order interleaving the faster one.)
+    const uint32_t NXCD = a.xcd_runs ? 8u : 1u;
+    const uint32_t gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+    const uint32_t lid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t per_xcd = nb / NXCD, extra = nb % NXCD, xcd = lid % NXCD, pos = lid / NXCD;
+    const uint32_t tid_run = (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
+    const uint32_t bx = tid_run % gx, by = (tid_run / gx) % gy, bz = tid_run / (gx * gy);
+    const int64_t x0 = (int64_t)bx * BX, y0 = (int64_t)by * BY;
     const int64_t x = x0 + tx, y = y0 + ty;
     const bool mine = x < g.nx && y < g.ny;
-    const int64_t z0 = (int64_t)blockIdx.z * a.z_chunk;
+    const int64_t z0 = (int64_t)bz * a.z_chunk;
     int64_t z1 = z0 + a.z_chunk;
     if (z1 > g.nz) z1 = g.nz;
     if (z0 >= z1) return;   // uniform across the block
