@@ -18,7 +18,7 @@ Beside the headline value the line carries:
                 from the committed rocprofv3 counter summary when it was taken
                 on the current kernel source, else null;
   cpu_baseline  the FP64 CPU oracle on the same workload, a bounded number of
-                steps, on the host's cores;
+                steps, on the host's cores (and on one thread);
   compare       naive GPU sweep (FP64), blocked FP32 run and its error against
                 the FP64 result, measured outside the timed region.
 
@@ -226,6 +226,20 @@ def main():
                "kind": "oracle",
                "sample": "%dx%dx%d 7-point constant FP64, %s, plain C sweep (OpenMP over z), %.1f s"
                          % (w.nx, w.ny, w.nz, what, dt)}
+        # the same sweep on one thread, about five seconds of it
+        n_all = O.num_threads()
+        O.set_num_threads(1)
+        try:
+            t1 = max(1, int(5.0 * cpu["value"] * 1e9 / n_all / (w.nx * w.ny * w.nz)))
+            a0 = u0.copy()
+            a1 = u0.copy()
+            t = time.perf_counter()
+            O.sweep(w.stencil, a0, a1, t1, c, None)
+            dt1 = time.perf_counter() - t
+        finally:
+            O.set_num_threads(n_all)
+        cpu["value_one_thread"] = round(w.nx * w.ny * w.nz * t1 / dt1 / 1e9, 4)
+        cpu["sample_one_thread"] = "%d steps, %.1f s" % (t1, dt1)
 
     out = {
         "metric": "GLUP/s per stencil at 1 GPU + % HBM roofline; blocked vs naive, FP32 vs FP64",
