@@ -18,9 +18,9 @@ def _dtype_name(t):
 
 
 class Sweep:
-    """A plan for ``T`` Jacobi steps of one stencil on one grid.
+    """A plan for ``T`` steps of one stencil ("7c", "7v", "25c", "25v", "25l") on one grid.
 
-    ``algo``: "mwd" (diamond rows, wavefront along z) or "naive".
+    ``algo``: "mwd" (diamond rows, wavefront along z; "7c" and "25c") or "naive".
     ``params``: dict of ``girih_params`` fields (zeros take defaults).
     """
 
@@ -48,7 +48,12 @@ class Sweep:
             raise TypeError("%s has the wrong dtype for a %s plan" % (what, self.dtype))
 
     def run(self, buf0, buf1, T, coefs=(), stream=None):
-        """Run T steps; returns the tensor (buf0 or buf1) that holds u^T."""
+        """Run T steps; returns the tensor (buf0 or buf1) that holds u^T.
+
+        ``buf0`` holds u^0 with its halo, ``buf1`` the same halo; for the
+        second-order-in-time stencil "25l" the interior of ``buf1`` is read as
+        u^{-1} (a copy of u^0 starts from rest).  Both buffers are clobbered;
+        the other one returns u^{T-1} for "25l"."""
         import torch
         self._check(buf0, "buf0")
         self._check(buf1, "buf1")
