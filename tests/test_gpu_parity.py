@@ -292,3 +292,31 @@ def test_mwd_nonzero_halo(stencil, dw, vx, wx, n, T):
     assert_bitwise(got, oracle_run(stencil, u0, c, arr, T), "nonzero halo %s" % stencil)
     got32, _ = run_gpu(stencil, "f32", u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx))
     assert_bitwise(got32, oracle_run(stencil, u0, c, arr, T, "f32"), "nonzero halo f32 %s" % stencil)
+
+
+def test_mwd_random_shapes_match_naive():
+    """Seeded random grids, step counts and registered blocked shapes (FP64
+    and FP32, both constant-coefficient stencils): the blocked sweep equals
+    the naive GPU sweep bit for bit, and every tenth case also the oracle."""
+    import paper_1510_04995_amd as P
+    rng = np.random.default_rng(2024)
+    shapes = {}
+    for st in ("7c", "25c"):
+        for dt in ("f64", "f32"):
+            p = P.Sweep(st, dt, 64, 64, 64, [0.4, 0.1] if st == "7c" else [0.2, 0.05, 0.04, 0.03, 0.0133], "mwd")
+            shapes[(st, dt)] = sorted({(q["diamond_width"], q["cells_per_lane"], q["threads_x"] // 64)
+                                       for q in p.candidates()})
+            p.close()
+    for case in range(120):
+        st = ("7c", "25c")[case % 2]
+        dt = ("f64", "f32")[(case // 2) % 2]
+        dw, vx, wx = shapes[(st, dt)][rng.integers(len(shapes[(st, dt)]))]
+        n = (int(rng.integers(1, 260)), int(rng.integers(1, 70)), int(rng.integers(1, 30)))
+        T = int(rng.integers(0, 3 * dw))
+        print("random", case, st, dt, dw, vx, wx, n, T, flush=True)
+        u0, c, arr = inputs(st, *n, seed=case)
+        got, _ = run_gpu(st, dt, u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx))
+        naive, _ = run_gpu(st, dt, u0, c, arr, T, algo="naive")
+        assert_bitwise(got, naive, "random case %d %s %s Dw=%d vx=%d wx=%d n=%s T=%d" % (case, st, dt, dw, vx, wx, n, T))
+        if case % 10 == 0:
+            assert_bitwise(got, oracle_run(st, u0, c, arr, T, dt), "random case %d vs oracle" % case)
