@@ -578,7 +578,9 @@ mwd_row_kernel(MwdArgs<Real> a) {
         }
 
         // One wavefront step; ph: step index modulo UNR.
-        auto step = [&](auto phc, auto steadyc, int zs) __attribute__((always_inline)) {
+        auto step = [&](auto phc, auto steadyc, int zs, auto sbc) __attribute__((always_inline)) {
+            // row B's first slot: a compile-time index where the caller knows it (SBK >= 0)
+            constexpr int SBK = decltype(sbc)::value;
             constexpr int ph = decltype(phc)::value;
             constexpr bool STEADY = decltype(steadyc)::value;
             // stage buffer of this step (steps start at an even zs, so ph = zs mod 2)
@@ -715,60 +717,68 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         if constexpr (s + LDEP < NS) load_nb(std::integral_constant<int, s + LDEP>{});
                         // issue those reads before this slot's arithmetic
                         __builtin_amdgcn_sched_barrier(0);
+                        if constexpr (SBK >= 0 && s == SBK) {
+                            // row B's input slot takes the loaded input plane (no arithmetic)
 #pragma unroll
-                        for (int v = 0; v < VX; ++v) {
-                            Nbhd<Real, R> n;
-                            n.c = ring[s - 1][P(R)][v];
+                            for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
+                        } else {
 #pragma unroll
-                            for (int r = 1; r <= R; ++r) {
-                                n.zm[r - 1] = ring[s - 1][P(R - r)][v];
-                                n.zp[r - 1] = r == R ? prev[v] : ring[s - 1][P(R + r)][v];
-                                n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][v];
-                                n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][v];
-                                n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][v];
-                                n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][v];
-                            }
-                            Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
-                            if constexpr (S::NCOEF > 0) {
-                                // Coefficients of the slot's plane.  In the steady range
-                                // every slot's offset (0 for unused slots: the window's
-                                // first plane, zs - R*L >= -R) stays inside the arrays;
-                                // elsewhere only slots whose plane is inside the grid load.
-                                if (STEADY || zv) {
-                                    const uint32_t go = gos[s] + xb[v];
+                            for (int v = 0; v < VX; ++v) {
+                                Nbhd<Real, R> n;
+                                n.c = ring[s - 1][P(R)][v];
 #pragma unroll
-                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = ld_at(at(a.coef.arr[m], e0b), go);
-                                } else {
-#pragma unroll
-                                    for (int m = 0; m < S::NCOEF; ++m) cf[m] = Real(0);
+                                for (int r = 1; r <= R; ++r) {
+                                    n.zm[r - 1] = ring[s - 1][P(R - r)][v];
+                                    n.zp[r - 1] = r == R ? prev[v] : ring[s - 1][P(R + r)][v];
+                                    n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][v];
+                                    n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][v];
+                                    n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][v];
+                                    n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][v];
                                 }
+                                Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
+                                if constexpr (S::NCOEF > 0) {
+                                    // Coefficients of the slot's plane.  In the steady range
+                                    // every slot's offset (0 for unused slots: the window's
+                                    // first plane, zs - R*L >= -R) stays inside the arrays;
+                                    // elsewhere only slots whose plane is inside the grid load.
+                                    if (STEADY || zv) {
+                                        const uint32_t go = gos[s] + xb[v];
+#pragma unroll
+                                        for (int m = 0; m < S::NCOEF; ++m) cf[m] = ld_at(at(a.coef.arr[m], e0b), go);
+                                    } else {
+#pragma unroll
+                                        for (int m = 0; m < S::NCOEF; ++m) cf[m] = Real(0);
+                                    }
+                                }
+                                nv[v] = S::apply(n, a.coef.k, cf);
                             }
-                            nv[v] = S::apply(n, a.coef.k, cf);
-                        }
-                        if constexpr (!STEADY) {
-                            // a level whose plane is a halo plane (or beyond) holds the halo
-                            if (!zv) {
+                            if constexpr (!STEADY) {
+                                // a level whose plane is a halo plane (or beyond) holds the halo
+                                if (!zv) {
 #pragma unroll
-                                for (int v = 0; v < VX; ++v) nv[v] = Real(0);
-                                if constexpr (!ZH) {
-                                    // halo values, for computed levels only (an unused
-                                    // slot's row may lie outside the grid)
-                                    const bool isB = s >= sb;
-                                    const int k = isB ? baseB + (s - sb) : baseA + s;
-                                    const int q = zs - R * k;
-                                    if (((cm >> s) & 1u) && q >= -R && q < nz + R) {
-                                        const Real* base =
-                                            at(a.in[0], plane_off(q) + (int64_t)(ybase + (isB ? jB : jA) + hh) * pitchx * SB);
+                                    for (int v = 0; v < VX; ++v) nv[v] = Real(0);
+                                    if constexpr (!ZH) {
+                                        // halo values, for computed levels only (an unused
+                                        // slot's row may lie outside the grid)
+                                        const bool isB = s >= sb;
+                                        const int k = isB ? baseB + (s - sb) : baseA + s;
+                                        const int q = zs - R * k;
+                                        if (((cm >> s) & 1u) && q >= -R && q < nz + R) {
+                                            const Real* base =
+                                                at(a.in[0], plane_off(q) + (int64_t)(ybase + (isB ? jB : jA) + hh) * pitchx * SB);
 #pragma unroll
-                                        for (int v = 0; v < VX; ++v) nv[v] = ld_at(base, xb[v]);
+                                            for (int v = 0; v < VX; ++v) nv[v] = ld_at(base, xb[v]);
+                                        }
                                     }
                                 }
                             }
-                        }
-                        // row B's input slot takes the loaded input plane
-                        if (s == sb) {
+                            // row B's input slot takes the loaded input plane
+                            if constexpr (SBK < 0) {
+                                if (s == sb) {
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
+                                    for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
+                                }
+                            }
                         }
                         // slot s-1's ring takes its newest plane
 #pragma unroll
@@ -841,15 +851,37 @@ mwd_row_kernel(MwdArgs<Real> a) {
         using Steady = std::integral_constant<bool, true>;
         // (three loops rather than one with a per-step branch: separate loops
         // keep the register assignment of both bodies spill-free)
+        using AnySB = std::integral_constant<int, -1>;
         int zb = -RING;
         for (; zb < nzs; zb += UNR) {
             if (zb >= zA && zb < zB) break;
-            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) { step(phc, General{}, zb + decltype(phc)::value); });
+            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) {
+                step(phc, General{}, zb + decltype(phc)::value, AnySB{});
+            });
         }
-        for (; zb < zB; zb += UNR)
-            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) { step(phc, Steady{}, zb + decltype(phc)::value); });
+        // The steady loop is compiled once per position of row B's first slot
+        // that a full diamond row has (L - 2b for b = 0 .. H/2 - 1), so that
+        // slot skips the arithmetic and no slot selects at run time; other
+        // positions (clipped rows) take the generic copy.
+        auto steady = [&](auto sbc) __attribute__((always_inline)) {
+            for (; zb < zB; zb += UNR)
+                static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) {
+                    step(phc, Steady{}, zb + decltype(phc)::value, sbc);
+                });
+        };
+        bool done = false;
+        static_for<0, (H / 2 > 0 ? H / 2 : 1)>([&](auto bc) __attribute__((always_inline)) {
+            constexpr int K = L - 2 * decltype(bc)::value;
+            if (!done && K < NS && sB == K) {
+                steady(std::integral_constant<int, (K < NS ? K : -1)>{});
+                done = true;
+            }
+        });
+        if (!done) steady(AnySB{});
         for (; zb < nzs; zb += UNR)
-            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) { step(phc, General{}, zb + decltype(phc)::value); });
+            static_for<0, UNR>([&](auto phc) __attribute__((always_inline)) {
+                step(phc, General{}, zb + decltype(phc)::value, AnySB{});
+            });
     };
     if (zero_halo)
         sweep(std::integral_constant<bool, true>{});
