@@ -268,9 +268,10 @@ enum : int {
 // are fixed per wave and precomputed; the ring of slot s (the last 2R planes
 // of its level) lives in registers at a compile-time index.  Slots without a
 // stage row of their own (unused slots, level L-1) write and read a block of
-// spare LDS rows.  For R = 1 the two ring phases are unrolled (renaming); for
-// larger R the rings shift by one register per step, which keeps the loop
-// body small enough for the instruction cache.
+// spare LDS rows.  Where registers allow, the wavefront loop is unrolled over
+// all 2R ring phases, so a ring advances by renaming its registers (always for
+// R = 1); for larger R and wide or deep shapes the rings shift by one
+// register per step instead, which keeps the loop free of spills.
 //
 // Two bodies share this state: the general one (any wavefront step) and the
 // steady one, for steps at which the plane of every level lies inside the
@@ -289,9 +290,12 @@ mwd_row_kernel(MwdArgs<Real> a) {
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
     constexpr int NS = NSV > 0 ? NSV : L + 2;
     static_assert(NS >= 3 && NS <= L + 2, "slot count");
-    // steps unrolled per loop iteration: two (the ring phases for R = 1 and
-    // the two stage buffers)
-    constexpr int UNR = 2;
+    // steps unrolled per loop iteration, a multiple of the two stage buffers:
+    // one per ring phase (2R) where that loop still compiles without spills
+    // (at most four levels and 8 bytes per lane and ring plane), so the
+    // z-rings rotate by renaming registers; otherwise two, and rings longer
+    // than two planes shift by register moves
+    constexpr int UNR = (RING == 2 || (L <= 4 && VX * WX * (int)sizeof(Real) <= 8)) ? RING : 2;
     // HBM inputs are loaded PD steps before the step that uses them, into
     // one of PD register sets
     constexpr int PD = 1;
