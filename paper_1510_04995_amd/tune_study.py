@@ -1,6 +1,7 @@
 """Evaluation of the learned cost model against the paper's tuner.
 
   python -m paper_1510_04995_amd.tune_study [--out report.json] [--log train.jsonl]
+  python -m paper_1510_04995_amd.tune_study summary <report.json> <out.md> <command...>
 
 1. The tuner measures every feasible blocked candidate (exhaustive search) of
    the training problems: 7-point constant 64^3 (T = 16) and 512^3 (T = 64),
@@ -12,7 +13,8 @@
    the paper's "largest tile that fits" pick: best measured GLUP/s, number of
    candidates measured and tuning time.
 
-Prints one progress line per problem and a JSON report at the end.
+Prints one progress line per problem and a JSON report at the end; the
+`summary` form writes that report as a markdown table.
 """
 import argparse
 import json
@@ -111,5 +113,31 @@ def main():
     return 0
 
 
+def summary(report_path, out_path, command):
+    rep = json.loads(open(report_path).read())
+    lines = ["# Learned cost model against the tuner", "",
+             "Command: `%s`" % command, "",
+             "Training: every feasible blocked candidate of %s, FP64 and FP32, measured by exhaustive search: "
+             "%d records; loss %.4g -> %.4g (log GLUP/s squared), median absolute log error %.3f, %.1f s on the GPU."
+             % (", ".join("%s %s T = %d" % (st, "x".join(str(v) for v in n), T) for st, n, T in TRAIN),
+                rep["train_records"], rep["train_loss_first"], rep["train_loss_last"],
+                rep["train_median_abs_log_error"], rep["train_seconds"]), "",
+             "Evaluation on an unseen grid: best measured GLUP/s (candidates measured, tuning seconds).", "",
+             "| problem | grid, T | exhaustive | hill climbing | model top-5 | largest tile that fits "
+             "| model / exhaustive |", "|---|---|---|---|---|---|---|"]
+    for r in rep["eval"]:
+        def cell(k):
+            e = r[k]
+            return "%.1f (%d, %.1f s)" % (e["glups"], e["measured"], e["seconds"])
+        lines.append("| %s %s | %s, %d | %s | %s | %s | %.1f | %.3f |" % (
+            r["stencil"], r["dtype"], "x".join(str(v) for v in r["grid"]), r["T"], cell("exhaustive"),
+            cell("hillclimb"), cell("model_top5"), r["largest_tile"]["glups"], r["model_vs_exhaustive"]))
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    sys.exit(main())
+    if len(sys.argv) > 1 and sys.argv[1] == "summary":
+        summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    else:
+        sys.exit(main())

@@ -148,3 +148,23 @@ def test_socket_power_parser(monkeypatch):
     assert energy.socket_power_w() == 262.0
     R.stdout = "not json"
     assert energy.socket_power_w() is None
+
+
+def test_tune_study_table(tmp_path):
+    from paper_1510_04995_amd import tune_study
+
+    def e(g, m, t):
+        return {"glups": g, "measured": m, "seconds": t, "params": {}}
+    rep = {"train_records": 176, "train_loss_first": 26.9, "train_loss_last": 0.0009,
+           "train_median_abs_log_error": 0.007, "train_seconds": 3.5,
+           "eval": [{"stencil": "7c", "dtype": "f64", "grid": [256, 512, 1024], "T": 64,
+                     "exhaustive": e(400.0, 28, 6.5), "hillclimb": e(399.0, 15, 3.0),
+                     "model_top5": e(398.0, 5, 1.2), "largest_tile": e(304.2, 1, 0.3),
+                     "model_vs_exhaustive": 0.995}]}
+    p = tmp_path / "r.json"
+    p.write_text(json.dumps(rep))
+    out = tmp_path / "t.md"
+    tune_study.summary(str(p), str(out), "cmd")
+    t = out.read_text()
+    assert "176 records; loss 26.9 -> 0.0009" in t
+    assert "| 7c f64 | 256x512x1024, 64 | 400.0 (28, 6.5 s) | 399.0 (15, 3.0 s) | 398.0 (5, 1.2 s) | 304.2 | 0.995 |" in t
