@@ -36,7 +36,7 @@ extern "C" {
 
 #define GIRIH_OK 0
 #define GIRIH_E_INVALID (-1)     /* bad argument (null pointer, size, halo, pitch, T < 0, ...) */
-#define GIRIH_E_UNSUPPORTED (-2) /* valid request this build has no kernel for */
+#define GIRIH_E_UNSUPPORTED (-2) /* valid request the library has no kernel for */
 #define GIRIH_E_LDS (-3)         /* tile parameters exceed the on-chip budget */
 #define GIRIH_E_HIP (-4)         /* a HIP runtime call failed */
 #define GIRIH_E_NOMEM (-5)       /* device or host allocation failed */

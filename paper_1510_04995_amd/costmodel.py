@@ -6,7 +6,8 @@ feasible point.  This module adds a learned proposer beside it.  A small
 fully connected network predicts the log throughput of a candidate from its
 features.  It is trained on the tuner's own measurements, and it proposes the
 top-k candidates of a new problem.  The tuner then measures only those
-(``GIRIH_TUNE_MODEL``).  Exhaustive search stays as the fallback and the judge.
+(``GIRIH_TUNE_MODEL``).  Exhaustive search stays as the fallback and as the
+reference the proposals are checked against.
 
 All arithmetic of the network (forward, back-propagation, Adam) runs in the
 ``girih_mlp_*`` HIP kernels of ``libgirih.so``; this module holds the
