@@ -301,6 +301,13 @@ mwd_row_kernel(MwdArgs<Real> a) {
     constexpr int PD = 1;
     // a slot's x/y neighbours are read from the stage LDEP slots ahead
     constexpr int LDEP = 1;
+    // Rows that compute no level copy both input levels to the output pair.
+    // Only the first and last diamond rows of a run hold such rows, and the
+    // host runs those with the clipped-slot instance (NSV > 0), which has
+    // registers to spare: there the copy is loaded one step ahead like every
+    // other input.  The full instance, which meets such rows only when a
+    // clipped row does not fit it, loads and stores in the same step.
+    constexpr bool CPF = NSV > 0;
     constexpr int SB = (int)sizeof(Real);
     static_assert(NS <= 32, "slot masks are 32-bit");
     __shared__ Real stage[KK::LDS_ROWS * XLP];
@@ -570,10 +577,15 @@ mwd_row_kernel(MwdArgs<Real> a) {
         // kv of a row (its input ring);
         // p2: duty level kv-1; po: the out-of-span row.
         Real qA[PD][VX], qB[PD][VX], p2A[PD][VX], p2B[PD][VX], poA[PD][VX], poB[PD][VX];
+        // copied levels (row A / B, input array 0 / 1) of plane zs + PD
+        Real cpv[PD][2][2][VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
 #pragma unroll
-            for (int c = 0; c < PD; ++c) qA[c][v] = qB[c][v] = p2A[c][v] = p2B[c][v] = poA[c][v] = poB[c][v] = Real(0);
+            for (int c = 0; c < PD; ++c) {
+                qA[c][v] = qB[c][v] = p2A[c][v] = p2B[c][v] = poA[c][v] = poB[c][v] = Real(0);
+                cpv[c][0][0][v] = cpv[c][0][1][v] = cpv[c][1][0][v] = cpv[c][1][1][v] = Real(0);
+            }
 #pragma unroll
             for (int m = 0; m < RING; ++m) {
 #pragma unroll
@@ -604,6 +616,25 @@ mwd_row_kernel(MwdArgs<Real> a) {
             // ---- A: stage every plane the levels read this step ------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
+                // copied levels of plane zs, loaded one step ago (before this
+                // step's loads reuse the registers)
+                if constexpr (CPF) {
+                    if ((f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
+                        const int64_t e0b = plane_off(zs - R * L);
+                        const __amdgpu_buffer_rsrc_t o0 = raw_rsrc(atw(a.out[0], e0b)),
+                                                     o1 = raw_rsrc(atw(a.out[1], e0b));
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
+#pragma unroll
+                                for (int v = 0; v < VX; ++v) {
+                                    buf_store(o0, cpo[t][v] | kill[v], cpv[ph % PD][t][0][v]);
+                                    buf_store(o1, cpo[t][v] | kill[v], cpv[ph % PD][t][1][v]);
+                                }
+                            }
+                        }
+                    }
+                }
                 // every slot (unused ones into the spare rows); the duty rows are
                 // written after them.  Only workgroups at the x edge hold halo
                 // lanes, so only they pay for the select.
@@ -628,6 +659,24 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 // next load is issued.
                 prefetch(zs, STEADY, qA[ph % PD], qB[ph % PD], p2A[ph % PD], p2B[ph % PD], poA[ph % PD], poB[ph % PD],
                          [&](uint32_t la, const Real (&src)[VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
+                if constexpr (CPF) {
+                    const int q = zs + PD;   // the plane the copy stores at step zs + PD
+                    if ((f & (F_COPY_A | F_COPY_B)) && q >= 0 && q < nz) {
+                        const int64_t nb = plane_off(q - R * L);
+                        const Real* fb0 = at(a.in[0], nb);
+                        const Real* fb1 = at(a.in[1], nb);
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
+#pragma unroll
+                                for (int v = 0; v < VX; ++v) {
+                                    cpv[ph % PD][t][0][v] = ld_at(fb0, cpo[t][v]);
+                                    cpv[ph % PD][t][1][v] = ld_at(fb1, cpo[t][v]);
+                                }
+                            }
+                        }
+                    }
+                }
                 // non-zero halo, edge workgroups only: fixed values in halo columns
                 // of computed rows, and halo rows (latency exposed)
                 if (!ZH && (f & (F_EDGE_X | F_EDGE_Y))) {
@@ -816,8 +865,9 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         ring[NS - 1][RING - 1][v] = prev[v];
                     }
                 }
-                // rows of this diamond with no level in this row: carry both levels
-                if ((f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
+                // rows of this diamond with no level in this row: carry both
+                // levels (the clipped instance stored them in phase A)
+                if (!CPF && (f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
                     const __amdgpu_buffer_rsrc_t o0 = raw_rsrc(atw(a.out[0], e0b)), o1 = raw_rsrc(atw(a.out[1], e0b));
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
