@@ -758,6 +758,13 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 static_for<1, (LDEP + 1 < NS ? LDEP + 1 : NS)>([&](auto tc) __attribute__((always_inline)) { load_nb(tc); });
                 static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
                     constexpr int s = decltype(sc)::value;
+                    // Wave priority falls as a wave advances through its slots,
+                    // so a wave that is behind issues first.  (With equal
+                    // priorities the oldest wave on a SIMD issues first, finishes
+                    // first and waits at the barrier for the youngest, which runs
+                    // its last slots alone.)
+                    constexpr int PRI = 3 - (4 * s) / NS;
+                    if constexpr (s == 0 || PRI != 3 - (4 * (s - 1)) / NS) __builtin_amdgcn_s_setprio(PRI);
                     Real nv[VX];
                     if constexpr (s == 0) {
 #pragma unroll
