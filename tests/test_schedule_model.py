@@ -10,7 +10,9 @@ workgroup and wave, and check them over many small configurations:
 * address bounds: every coefficient load, halo load and prefetch load of the
   kernel's two loop bodies (ramp and steady) touches a plane inside the haloed
   array, and the steady range contains only steps whose level planes and
-  stored planes lie inside the grid;
+  stored planes lie inside the grid, for both loop unroll depths; the levels
+  that rows computing nothing carry over are loaded one step before each
+  plane of the grid is stored;
 * slot counts: the count the host uses to pick a kernel with fewer register
   slots per wave bounds what every wave of every diamond of the row holds,
   and the first and last rows of a run fit the H + 3 slots of the clipped-row
@@ -188,9 +190,13 @@ def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True):
 
 
 
-def check_prefetch(R, DW, ny, nz, T, PD=1):
-    """Planes of the prefetch loads (both bodies) stay inside [-R, nz+R)."""
-    H = DW // (2 * R); L = 2 * H; RING = 2 * R; UNR = 2
+def check_prefetch(R, DW, ny, nz, T, PD=1, UNR=2):
+    """Planes of the prefetch loads (both bodies) stay inside [-R, nz+R); the
+    levels that rows computing nothing carry over (clipped-row kernel) are
+    loaded for every plane of [0, nz) one step before the step that stores
+    them.  UNR: steps per loop iteration (2, or 2R where the kernel unrolls
+    every ring phase)."""
+    H = DW // (2 * R); L = 2 * H; RING = 2 * R
     nzs = nz + R * L
     zA = ((R * L + UNR - 1) // UNR) * UNR
     zB0 = nz if R >= PD else nz + R - PD
@@ -216,6 +222,16 @@ def check_prefetch(R, DW, ny, nz, T, PD=1):
             for k in range(L):
                 if not (0 <= zs - R * k < nz) or not (0 <= zs - R * (k + 1) < nz):
                     bad.append(('plane', zs, k))
+    # carried levels: loaded at step zs for plane zs + PD, stored at step q = zs + PD
+    live = [zs for zs, steady in steps if steady or zs < nzs]
+    if len(set(live)) != len(live) or live != sorted(live):
+        bad.append(('step order', live[:5]))
+    loaded = {zs + PD for zs in live if 0 <= zs + PD < nz}
+    stored = {zs for zs in live if 0 <= zs < nz}
+    if stored != set(range(nz)) or loaded != stored:
+        bad.append(('carry', sorted(set(range(nz)) - stored)[:3], sorted(stored - loaded)[:3]))
+    if steps and steps[0][0] % UNR != 0:
+        bad.append(('phase', steps[0][0]))
     return bad
 
 
@@ -250,9 +266,10 @@ def test_the_earlier_z_mask_is_caught():
 
 @pytest.mark.parametrize("R,DW", [(R, d) for R, ds in CONFIGS for d in ds])
 def test_prefetch_planes_and_steady_range(R, DW):
-    for nz in range(1, 40):
-        e = check_prefetch(R, DW, 7, nz, 5)
-        assert not e, (R, DW, nz, e[:3])
+    for unr in sorted({2, 2 * R}):
+        for nz in range(1, 40):
+            e = check_prefetch(R, DW, 7, nz, 5, UNR=unr)
+            assert not e, (R, DW, unr, nz, e[:3])
 
 
 def slots_needed(R, DW, t_c, T):
