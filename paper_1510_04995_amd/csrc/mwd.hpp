@@ -504,10 +504,19 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 }
             }
         }
-        // x-halo lanes staged as zero when the halo is zero
+        // Zero halo, workgroups at the x edge: the x-halo lanes zero their
+        // column of every stage row once and never stage anything (their
+        // writes are masked off), so interior workgroups stage without
+        // selects or extra writes.
         bool hz[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) hz[v] = ZH && edge_x && xh[v];
+        if (ZH && edge_x) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v)
+                if (hz[v])
+                    for (int row = 0; row < KK::LDS_ROWS; ++row) stage[row * XLP + R + cb + lane + 64 * v] = Real(0);
+        }
 
         // wavefront steps end here: the last plane of level L-1 is computed at
         // step nz-1 + R*(L-1) and passes through the stage R steps later
@@ -523,15 +532,10 @@ mwd_row_kernel(MwdArgs<Real> a) {
         auto lds = [&](uint32_t byte_addr) -> Real& {
             return *reinterpret_cast<Real*>(reinterpret_cast<char*>(stage) + byte_addr);
         };
-        // Zero x-halo lanes (workgroups at the x edge): either every staged
-        // value is selected (kernels with two stage buffers), or the halo
-        // lanes overwrite what they staged with zeros after staging (one
-        // buffer: interior workgroups then stage without selects).  Each is
-        // the faster one for its kind of kernel on this device.
-        constexpr bool SELZ = KK::DB;
         auto put = [&](uint32_t la, const Real (&src)[VX]) {   // la: per-lane LDS byte address
 #pragma unroll
-            for (int v = 0; v < VX; ++v) lds(la + 64 * v * SB) = SELZ && hz[v] ? Real(0) : src[v];
+            for (int v = 0; v < VX; ++v)
+                if (!hz[v]) lds(la + 64 * v * SB) = src[v];
         };
         // x-halo columns of a staged computed row when the halo is not zero
         auto fix_halo_cols = [&](int li, int q, int y) {   // li: element index, buffer included
@@ -643,19 +647,15 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 }
                 // every slot (unused ones into the spare rows); the duty rows are
                 // written after them
-                auto stage_slots = [&](auto hzc) __attribute__((always_inline)) {
-                    constexpr bool HZ = decltype(hzc)::value;
-                    static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
-                        constexpr int s = decltype(sc)::value;
 #pragma unroll
-                        for (int v = 0; v < VX; ++v)
-                            lds(lcs[s] + BOFF + CORNER + 64 * v * SB) = HZ && hz[v] ? Real(0) : ring[s][P(R)][v];
-                    });
-                };
-                if (SELZ && ZH && (f & F_EDGE_X))
-                    stage_slots(std::true_type{});
-                else
-                    stage_slots(std::false_type{});
+                for (int v = 0; v < VX; ++v) {
+                    if (!hz[v]) {
+                        static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
+                            constexpr int s = decltype(sc)::value;
+                            lds(lcs[s] + BOFF + CORNER + 64 * v * SB) = ring[s][P(R)][v];
+                        });
+                    }
+                }
                 // loads for step zs + PD into this step's register set (its
                 // values are consumed above or copied to vcA/vcB): plane
                 // zs + PD - R*dz of each stream; planes outside the haloed grid
@@ -664,22 +664,6 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 // next load is issued.
                 prefetch(zs, STEADY, qA[ph % PD], qB[ph % PD], p2A[ph % PD], p2B[ph % PD], poA[ph % PD], poB[ph % PD],
                          [&](uint32_t la, const Real (&src)[VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
-                // (one stage buffer) the halo lanes overwrite what they just
-                // staged with zeros: same lane and address, so in program order
-                if (!SELZ && ZH && (f & F_EDGE_X)) {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        if (hz[v]) {
-                            const uint32_t vo = BOFF + 64 * v * SB;
-#pragma unroll
-                            for (int i = 0; i < NS; ++i) lds(lcs[i] + CORNER + vo) = Real(0);
-                            if (f & F_D2_A) lds(fresh_s(uA2) + lane_b + vo) = Real(0);
-                            if (f & F_D2_B) lds(fresh_s(uB2) + lane_b + vo) = Real(0);
-                            if (f & F_O_A) lds(fresh_s(uOA) + lane_b + vo) = Real(0);
-                            if (f & F_O_B) lds(fresh_s(uOB) + lane_b + vo) = Real(0);
-                        }
-                    }
-                }
                 if constexpr (CPF) {
                     const int q = zs + PD;   // the plane the copy stores at step zs + PD
                     if ((f & (F_COPY_A | F_COPY_B)) && q >= 0 && q < nz) {
