@@ -41,11 +41,25 @@ KERNEL_SOURCES = ("paper_1510_04995_amd/csrc/mwd.hpp", "paper_1510_04995_amd/csr
                   "paper_1510_04995_amd/csrc/kernels_7c_f64.hip", "paper_1510_04995_amd/csrc/instantiate.hpp")
 
 
+def _code_only(text):
+    """The source without // comments and blank lines, each line stripped, so
+    that edits of comments do not change the hash (none of these sources puts
+    // inside a string)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].strip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def kernel_source_hash():
+    """Hash of the code of the diamond-row kernel's sources (comments excluded):
+    a stored profile counts for this kernel only if its hash matches."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -45,9 +45,10 @@
 // and copies the input levels at rows where it computes fewer than two.
 //
 // Dirichlet halo: if the halo of the input is all zero (a flag computed on
-// the device before the sweep) halo rows of the stage are zero-filled once
-// and halo lanes and planes are set to zero; otherwise halo values are loaded
-// where they are needed (slower, same result).
+// the device before the sweep) the halo rows and the x-halo columns of the
+// stage are zero-filled once (halo lanes never write the stage) and halo
+// planes are set to zero; otherwise halo values are loaded where they are
+// needed (slower, same result).
 #pragma once
 #include <type_traits>
 

@@ -32,6 +32,13 @@ def test_launch_updates_sum_to_the_run(T, H):
     assert sum(per) == pytest.approx(10 * 20 * 30 * T)
 
 
+def test_kernel_source_hash_ignores_comments_only():
+    import bench as b
+    code = "int a = 1;  // one\n\n// a comment line\nint b = 2;\n"
+    assert b._code_only(code) == "int a = 1;\nint b = 2;"
+    assert b._code_only(code) != b._code_only(code.replace("2", "3"))
+
+
 def test_kernel_source_hash_is_stable():
     b = load_bench()
     assert b.kernel_source_hash() == b.kernel_source_hash()
