@@ -215,6 +215,39 @@ def test_mwd_full_size_headline_vs_naive():
                                 [(0, 0, 0), (511, 511, 511), (0, 255, 511), (300, 7, 129), (256, 256, 256)])
 
 
+@pytest.mark.parametrize("stencil,dtype,n,T", [("7c", "f64", (509, 511, 513), 63), ("7c", "f32", (509, 511, 513), 63),
+                                                ("25c", "f64", (509, 511, 513), 33)])
+def test_mwd_odd_size_twin(stencil, dtype, n, T):
+    """Odd-size twins of the benchmark grids (509 x 511 x 513, T = H*k + 3 for
+    the default diamond heights H = 6 and 2) in the default launch
+    configuration: ragged x chunks, partial diamonds at both y ends and
+    clipped first and last rows at full scale.  The blocked sweep equals the
+    naive GPU sweep in every element, and sampled points equal the oracle on
+    their light cones."""
+    import paper_1510_04995_amd as P
+    from tests.gpu_util import torch_dev
+    torch, dev = torch_dev()
+    nx, ny, nz = n
+    h = 1 if stencil == "7c" else 4
+    u0, c, arr = inputs(stencil, nx, ny, nz, seed=5)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
+    res = {}
+    for algo in ("mwd", "naive"):
+        print("odd twin", stencil, dtype, n, T, algo, flush=True)
+        sw = P.Sweep(stencil, dtype, nx, ny, nz, [float(x) for x in c], algo)
+        b0, b1 = g0.clone(), g0.clone()
+        res[algo] = sw.run(b0, b1, T)
+        torch.cuda.synchronize()
+        sw.close()
+    rel, mx, nd = P.error_norms(res["mwd"], res["naive"], h, nx, ny, nz)
+    assert nd == 0 and mx == 0.0
+    out = res["mwd"].cpu().numpy()
+    del res, g0
+    pts = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, 0, nx - 1), (nz - 1, ny // 2, 0), (200, 300, 411)]
+    check_samples_against_cones(stencil, u0, c, arr, T, out, pts, dtype)
+
+
 @pytest.mark.parametrize("name,dtype", [("25pt-const-512", "f64"), ("25pt-var-384", "f64"),
                                         ("7pt-var-256x512x1024", "f64"), ("7pt-var-256x512x1024", "f32"),
                                         ("25pt-leapfrog-512", "f64")])
