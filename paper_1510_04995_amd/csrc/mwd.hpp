@@ -717,8 +717,11 @@ mwd_row_kernel(MwdArgs<Real> a) {
                 const int f = (int)fresh_s((uint32_t)flags);
                 // window of this step: planes [zs - R*L, zs]
                 const int64_t e0b = plane_off(zs - R * L);
-                {
-                    // the rows' last two levels, from the stage (see above)
+                // the rows' last two levels, from the stage (see above).  With
+                // one stage buffer they are read back after the update, when
+                // waves that finished early would otherwise wait at the
+                // barrier; with two, before it (there is no such wait to fill).
+                auto store_levels = [&]() __attribute__((always_inline)) {
                     const __amdgpu_buffer_rsrc_t rs_even = raw_rsrc(atw(a.out[p0 ^ 1], e0b));
                     const __amdgpu_buffer_rsrc_t rs_odd = raw_rsrc(atw(a.out[p0], e0b));
 #pragma unroll
@@ -732,7 +735,8 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         for (int v = 0; v < VX; ++v)
                             buf_store((i & 1) ? rs_odd : rs_even, sgo[i][v] | zd, lds(stl[i] + BOFF + 64 * v * SB));
                     }
-                }
+                };
+                if constexpr (KK::DB) store_levels();
                 const uint32_t cm = fresh_s(cmS);
                 const int sb = (int)fresh_s((uint32_t)sB);
                 uint32_t zS = 0xffffffffu;   // slots whose level's plane zs - R*k lies inside the grid
@@ -878,6 +882,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
                         ring[NS - 1][RING - 1][v] = prev[v];
                     }
                 }
+                if constexpr (!KK::DB) store_levels();
                 // rows of this diamond with no level in this row: carry both
                 // levels (the clipped instance stored them in phase A)
                 if (!CPF && (f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
