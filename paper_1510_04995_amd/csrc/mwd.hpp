@@ -80,6 +80,21 @@ __device__ __forceinline__ int64_t opaque_s(int64_t v) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
+// Value of a neighbouring lane of the wave (DPP move; CTRL 0x130 = wave_shl:1,
+// lane i takes lane i+1; 0x138 = wave_shr:1, lane i takes lane i-1); a lane
+// with no source lane gets zero (bound_ctrl).
+template <int CTRL, typename Real>
+__device__ __forceinline__ Real lane_shift(Real v) {
+    if constexpr (sizeof(Real) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, true);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, true);
+        return __builtin_bit_cast(Real, ((uint64_t)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(Real, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+    }
+}
+
 template <typename Real>
 struct MwdArgs {
     GridDesc g;
@@ -343,13 +358,23 @@ mwd_row_kernel(MwdArgs<Real> a) {
     // per-lane constants: clamped byte offset within a row, ownership, x-halo
     uint32_t xb[VX], kill[VX];   // kill: DROP on lanes whose stores this chunk does not own
     bool xh[VX];
+    // R = 1, FP64: x neighbours come from the neighbouring lanes' registers,
+    // except at the ends of a 64-lane block and next to halo lanes (whose
+    // registers hold no halo values), where they are read from the stage.
+    // (FP32 kernels, two stage buffers, lose with it; radius 4 would need
+    // eight moves per value.)
+    constexpr bool XDPP = R == 1 && sizeof(Real) == 8;
+    bool mxm[VX], mxp[VX];
+    auto in_halo = [&](int x) { return (x >= -R && x < 0) || (x >= nx && x < nx + R); };
 #pragma unroll
     for (int v = 0; v < VX; ++v) {
         const int x = x0 + cb + lane + 64 * v;
         const int xc = x < -R ? -R : (x >= nx + R ? nx + R - 1 : x);
         xb[v] = (uint32_t)((xc + hh) * SB);
         kill[v] = x >= x_own_lo && x < x_own_hi ? 0u : DROP;
-        xh[v] = (x >= -R && x < 0) || (x >= nx && x < nx + R);
+        xh[v] = in_halo(x);
+        mxm[v] = lane == 0 || in_halo(x - 1);
+        mxp[v] = lane == 63 || in_halo(x + 1);
     }
 
     // ---- this wave's two rows ------------------------------------------------
@@ -756,12 +781,25 @@ mwd_row_kernel(MwdArgs<Real> a) {
 #pragma unroll
                     for (int v = 0; v < VX; ++v) {
                         const uint32_t c0 = lb + 64 * v * SB + CORNER;
+                        if constexpr (XDPP) {
+                            // the level below's plane at the neighbouring lanes is
+                            // what they staged: their ring position R
+                            nb[t % (LDEP + 1)][2][v] = lds(c0 + XLP * SB);
+                            nb[t % (LDEP + 1)][3][v] = lds(c0 - XLP * SB);
+                            const Real cc = ring[t - 1][P(R)][v];
+                            Real xp = lane_shift<0x130>(cc), xm = lane_shift<0x138>(cc);
+                            if (mxp[v]) xp = lds(c0 + SB);
+                            if (mxm[v]) xm = lds(c0 - SB);
+                            nb[t % (LDEP + 1)][0][v] = xp;
+                            nb[t % (LDEP + 1)][1][v] = xm;
+                        } else {
 #pragma unroll
-                        for (int r = 1; r <= R; ++r) {
-                            nb[t % (LDEP + 1)][r - 1][v] = lds(c0 + r * SB);
-                            nb[t % (LDEP + 1)][R + r - 1][v] = lds(c0 - r * SB);
-                            nb[t % (LDEP + 1)][2 * R + r - 1][v] = lds(c0 + r * XLP * SB);
-                            nb[t % (LDEP + 1)][3 * R + r - 1][v] = lds(c0 - r * XLP * SB);
+                            for (int r = 1; r <= R; ++r) {
+                                nb[t % (LDEP + 1)][r - 1][v] = lds(c0 + r * SB);
+                                nb[t % (LDEP + 1)][R + r - 1][v] = lds(c0 - r * SB);
+                                nb[t % (LDEP + 1)][2 * R + r - 1][v] = lds(c0 + r * XLP * SB);
+                                nb[t % (LDEP + 1)][3 * R + r - 1][v] = lds(c0 - r * XLP * SB);
+                            }
                         }
                     }
                 };
