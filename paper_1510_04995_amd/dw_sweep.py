@@ -28,6 +28,10 @@ CASES = [
     ("7c", "f64", (512, 512, 512), 64, "mwd", {"diamond_width": 12, "cells_per_lane": 1, "threads_x": 128,
                                                "tile_x": 103}),
     ("7c", "f64", (512, 512, 512), 64, "mwd", {"diamond_width": 16, "cells_per_lane": 1, "threads_x": 64}),
+    # FP32: the blocked sweep at the benchmark's plan against the naive sweep
+    ("7c", "f32", (512, 512, 512), 64, "naive", None),
+    ("7c", "f32", (512, 512, 512), 64, "mwd", {"diamond_width": 12, "cells_per_lane": 1, "threads_x": 128,
+                                               "tile_x": 103}),
     ("25c", "f64", (512, 512, 512), 32, "naive", None),
     ("25c", "f64", (512, 512, 512), 32, "mwd", {"diamond_width": 8, "cells_per_lane": 1, "threads_x": 128}),
     ("25c", "f64", (512, 512, 512), 32, "mwd", {"diamond_width": 16, "cells_per_lane": 1, "threads_x": 64}),
