@@ -315,7 +315,8 @@ mwd_row_kernel(MwdArgs<Real> a) {
     // HBM inputs are loaded PD steps before the step that uses them, into
     // one of PD register sets
     constexpr int PD = 1;
-    // a slot's x/y neighbours are read from the stage LDEP slots ahead
+    // a slot's x/y neighbours are fetched LDEP slots ahead (from the stage;
+    // x neighbours of FP64 radius-1 kernels from the neighbouring lanes)
     constexpr int LDEP = 1;
     // Rows that compute no level copy both input levels to the output pair.
     // Only the first and last diamond rows of a run hold such rows, and the
