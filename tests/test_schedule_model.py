@@ -13,6 +13,9 @@ workgroup and wave, and check them over many small configurations:
   stored planes lie inside the grid, for both loop unroll depths; the levels
   that rows computing nothing carry over are loaded one step before each
   plane of the grid is stored;
+* x neighbours by lane moves (FP64, radius 1): with the kernel's edge-lane
+  masks every lane inside the grid gets exactly the neighbours the stage
+  holds, for zero and nonzero halos and every block of every x chunk;
 * slot counts: the count the host uses to pick a kernel with fewer register
   slots per wave bounds what every wave of every diamond of the row holds,
   and the first and last rows of a run fit the H + 3 slots of the clipped-row
@@ -334,3 +337,69 @@ def test_workgroup_renumbering_is_a_bijection_with_contiguous_runs(nxcd):
             order = [seen[(c, d)] for d in range(gy) for c in range(gx)]
             runs = [order[0]] + [b for a, b in zip(order, order[1:]) if b != a]
             assert len(runs) == len(set(runs))
+
+
+def dpp_neighbours(vals, stage_row, lane0_col, mask_rule):
+    """x neighbours of the 64 lanes of one block as the FP64 radius-1 kernel
+    forms them: lane i takes lane i-1's / i+1's register value (DPP wave
+    shifts; a lane with no source gets 0), and lanes the mask names read both
+    from the stage row instead."""
+    n = len(vals)
+    xm = [vals[i - 1] if i > 0 else 0.0 for i in range(n)]
+    xp = [vals[i + 1] if i + 1 < n else 0.0 for i in range(n)]
+    for i in range(n):
+        if mask_rule(i, "m"):
+            xm[i] = stage_row[lane0_col + i - 1]
+        if mask_rule(i, "p"):
+            xp[i] = stage_row[lane0_col + i + 1]
+    return xm, xp
+
+
+@pytest.mark.parametrize("nx", [1, 5, 63, 64, 65, 100, 130, 300])
+def test_dpp_edge_masks_give_the_stage_values(nx):
+    """For every block of every x chunk (zero and nonzero halo), lanes whose
+    cell is inside the grid get exactly the x neighbours the stage holds:
+    the DPP value where the neighbour lane staged its own register value,
+    the stage otherwise (block ends, halo lanes' columns)."""
+    import random
+    R, XL = 1, 128
+    HX = R * (12 - 1)
+    x_own = XL - 2 * HX
+    rnd = random.Random(nx)
+    for zero_halo in (True, False):
+        n_chunks = (nx + x_own - 1) // x_own
+        for chunk in range(n_chunks):
+            x0 = chunk * x_own - HX
+            # a stage row: guard columns, then the XL cells; lanes stage their
+            # register value, halo lanes the halo value (zero, or the loaded one)
+            regs = [rnd.random() for _ in range(XL)]
+            halo = {x: (0.0 if zero_halo else rnd.random()) for x in (-1, nx)}
+            in_halo = lambda x: x in halo
+            stage = [rnd.random()] * R + [halo[x0 + c] if in_halo(x0 + c) else regs[c] for c in range(XL)] + \
+                [rnd.random()] * R
+            for blk in range(XL // 64):
+                cb = 64 * blk
+                vals = regs[cb:cb + 64]
+
+                def rule(i, side):
+                    x = x0 + cb + i
+                    return (i == 0 or in_halo(x - 1)) if side == "m" else (i == 63 or in_halo(x + 1))
+
+                xm, xp = dpp_neighbours(vals, stage, R + cb, rule)
+                for i in range(64):
+                    x = x0 + cb + i
+                    if 0 <= x < nx:
+                        assert xm[i] == stage[R + cb + i - 1], (nx, chunk, blk, i)
+                        assert xp[i] == stage[R + cb + i + 1], (nx, chunk, blk, i)
+
+
+def test_dpp_edge_masks_without_halo_lanes_fail():
+    # a mask that forgets the halo-adjacent lanes hands lane x = 0 the halo
+    # lane's register instead of the halo value: the check sees it
+    R, XL, nx = 1, 128, 100
+    regs = [float(c + 1) for c in range(XL)]
+    x0 = -11
+    stage = [9.0] + [0.0 if x0 + c in (-1, nx) else regs[c] for c in range(XL)] + [9.0]
+    xm, _ = dpp_neighbours(regs[:64], stage, R, lambda i, side: i == 0 if side == "m" else i == 63)
+    i = -x0          # lane of x = 0
+    assert xm[i] != stage[R + i - 1]
