@@ -120,3 +120,18 @@ def test_plant_wrong_sign_is_caught():
     e[-1] = h                                # the output bias
     num = (M.loss_grad(p + e, n_in, n_hidden, n_layers, x, t)[0] - M.loss_grad(p - e, n_in, n_hidden, n_layers, x, t)[0]) / (2 * h)
     assert abs(g[-1] - num) < 1e-6 and abs(-g[-1] - num) > 1e-3
+
+
+def test_zero_network_loss_is_the_mean_of_squared_targets():
+    """With every parameter zero the network outputs 0, so the loss is the
+    mean of t^2 (the 1/n of the mean squared error, not the sum) and the only
+    nonzero gradient entry is the output bias's, 2 * mean(0 - t)."""
+    rng = np.random.default_rng(3)
+    n_in, n_hidden, n_layers, n = 4, 6, 3, 11
+    p = np.zeros(M.param_count(n_in, n_hidden, n_layers))
+    x = rng.normal(size=(n, n_in))
+    t = rng.normal(size=n)
+    loss, g = M.loss_grad(p, n_in, n_hidden, n_layers, x, t)
+    assert loss == pytest.approx(float(np.dot(t, t)) / n, rel=1e-15)
+    assert g[-1] == pytest.approx(-2.0 * t.sum() / n, rel=1e-15)
+    assert np.all(g[:-1] == 0)

@@ -12,15 +12,29 @@ def test_cache_block_worked_example():
     assert (g["cs_Dw8_NF1_R1_ND2"] - 2 * 8 * 8 / 2) / 2 - 8 == g["ww_Dw8_NF1_R1"]
 
 
-def test_cache_block_r_gt_1_reduces_consistently():
-    # Both equations describe the same diamond-plus-halo footprint; for R = 1
-    # the general form differs from the R = 1 form only through Ww's -2 vs -2R
-    # and the N_F term, so at N_F = 1 they agree.
-    for Dw in (4, 8, 16, 32):
-        r1 = models.cache_block_bytes(Dw, 1, 1, 2)
-        ND, R, NF = 2, 1, 1
-        general = ND * Dw * (Dw / 2 - R + NF) + 2 * R * (Dw + (Dw - 2 * R + NF))
-        assert r1 == pytest.approx(general)
+def test_cache_block_values_by_hand():
+    """C_S / N_xb of both equations of Section "Cache block size model",
+    evaluated by hand at N_F = 1 (golden file): R = 1 for the 7-point stencils
+    (N_D = 2 and 9) and R > 1 for the 25-point ones (N_D = 2 and 15)."""
+    g = read_golden("paper_models.txt")
+    assert models.cache_block_bytes(16, 1, 1, 2) == g["cs_Dw16_R1_ND2"]
+    assert models.cache_block_bytes(32, 1, 1, 2) == g["cs_Dw32_R1_ND2"]
+    assert models.cache_block_bytes(8, 1, 1, 9) == g["cs_Dw8_R1_ND9"]
+    assert models.cache_block_bytes(16, 1, 1, 9) == g["cs_Dw16_R1_ND9"]
+    assert models.cache_block_bytes(16, 1, 4, 2) == g["cs_Dw16_R4_ND2"]
+    assert models.cache_block_bytes(32, 1, 4, 2) == g["cs_Dw32_R4_ND2"]
+    assert models.cache_block_bytes(64, 1, 4, 2) == g["cs_Dw64_R4_ND2"]
+    assert models.cache_block_bytes(16, 1, 4, 15) == g["cs_Dw16_R4_ND15"]
+    assert models.cache_block_bytes(32, 1, 4, 15) == g["cs_Dw32_R4_ND15"]
+
+
+def test_cache_block_wavefront_depth_term():
+    """N_F enters the R = 1 block as N_D*Dw*(N_F-1) + 2*(N_F-1) and the R > 1
+    block as N_D*Dw*(N_F-1) + 2R*(N_F-1): one more z plane of every stream
+    (hand-evaluated differences, golden file)."""
+    g = read_golden("paper_models.txt")
+    assert models.cache_block_bytes(8, 3, 1, 2) - models.cache_block_bytes(8, 1, 1, 2) == g["cs_Dw8_R1_ND2_NF3_minus_NF1"]
+    assert models.cache_block_bytes(16, 2, 4, 2) - models.cache_block_bytes(16, 1, 4, 2) == g["cs_Dw16_R4_ND2_NF2_minus_NF1"]
 
 
 def test_code_balance_values():

@@ -263,3 +263,87 @@ def test_oracle_rejects_bad_arguments():
         osw.sweep("7c", u, u.copy().astype(np.float32), 1, (0.4, 0.1))
     with pytest.raises(ValueError):
         osw.sweep("7v", u, u.copy(), 1, None, [u] * 6)
+
+
+# ------------------------------------ precision: listing order, bit for bit
+
+def numpy_listing_step(stencil, V, U, c, C, R):
+    """One step of Listings 1-4 over the interior, written with whole-array
+    numpy operations in the arrays' own precision (numpy keeps float32 op
+    float32 in float32), in the listings' left-to-right order.  An
+    independent second implementation: no loops, no C, no OpenMP."""
+    nzp, nyp, nxp = V.shape
+    def sh(dz, dy, dx):
+        return V[R + dz:nzp - R + dz, R + dy:nyp - R + dy, R + dx:nxp - R + dx]
+    inner = (slice(R, nzp - R), slice(R, nyp - R), slice(R, nxp - R))
+    Vc = sh(0, 0, 0)
+    if stencil == "7c":
+        u = c[0] * Vc + c[1] * (sh(0, 0, 1) + sh(0, 0, -1))
+        u = u + c[1] * (sh(0, 1, 0) + sh(0, -1, 0))
+        u = u + c[1] * (sh(1, 0, 0) + sh(-1, 0, 0))
+    elif stencil == "7v":
+        Cs = [a[inner] for a in C]
+        u = Cs[0] * Vc
+        for m, d in enumerate([(0, 0, 1), (0, 0, -1), (0, 1, 0), (0, -1, 0), (1, 0, 0), (-1, 0, 0)]):
+            u = u + Cs[m + 1] * sh(*d)
+    elif stencil in ("25c", "25l"):
+        b = c[0] * Vc
+        for r in range(1, 5):
+            s = sh(0, 0, r) + sh(0, 0, -r)
+            s = s + sh(0, r, 0)
+            s = s + sh(0, -r, 0)
+            s = s + sh(r, 0, 0)
+            s = s + sh(-r, 0, 0)
+            b = b + c[r] * s
+        if stencil == "25c":
+            u = b
+        else:
+            two = V.dtype.type(2)
+            u = (two * Vc - U[inner]) + C[0][inner] * b
+    else:   # 25v
+        Cs = [a[inner] for a in C]
+        u = Cs[0] * Vc
+        for r in range(1, 5):
+            u = u + Cs[3 * r - 2] * (sh(0, 0, r) + sh(0, 0, -r))
+            u = u + Cs[3 * r - 1] * (sh(0, r, 0) + sh(0, -r, 0))
+            u = u + Cs[3 * r] * (sh(r, 0, 0) + sh(-r, 0, 0))
+    assert u.dtype == V.dtype
+    out = U.copy()
+    out[inner] = u
+    return out
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v", "25l"])
+def test_oracle_equals_numpy_listing_order_bitwise(stencil, dtype):
+    """The oracle's float32 (and float64) sweeps equal a whole-array numpy
+    evaluation in the same precision and order, bit for bit.  A float32 sweep
+    that computed in double and rounded once per point, reordered a sum or
+    fused a multiply-add would differ in many elements."""
+    R = 1 if stencil.startswith("7") else 4
+    n = (13, 11, 9) if R == 1 else (15, 12, 11)
+    u0, consts, arrays = field_and_coefs(stencil, *n, seed=21)
+    u0 = u0.astype(dtype)
+    c = None if consts is None else np.asarray(consts, dtype=dtype)
+    C = None if arrays is None else [a.astype(dtype) for a in arrays]
+    prev = u0.copy()
+    if stencil == "25l":   # u^{-1} != u^0, so the U term matters
+        rng = np.random.default_rng(22)
+        prev[R:-R, R:-R, R:-R] = rng.random(prev[R:-R, R:-R, R:-R].shape).astype(dtype)
+    T = 3
+    b0, b1 = u0.copy(), prev.copy()
+    idx = osw.sweep(stencil, b0, b1, T, c, C)
+    got = (b0, b1)[idx]
+    V, U = u0.copy(), prev.copy()
+    for _ in range(T):
+        U = numpy_listing_step(stencil, V, U, c, C, R)
+        V, U = U, V
+    assert got.dtype == dtype
+    assert np.array_equal(got, V)
+    if dtype == np.float32:
+        # ... and differs from the float64 sweep rounded to float32 (so the
+        # comparison above can tell the two precisions apart)
+        b0, b1 = u0.astype(np.float64), prev.astype(np.float64)
+        i64 = osw.sweep(stencil, b0, b1, T, None if c is None else c.astype(np.float64),
+                        None if C is None else [a.astype(np.float64) for a in C])
+        assert not np.array_equal((b0, b1)[i64].astype(np.float32), got)
