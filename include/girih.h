@@ -136,21 +136,53 @@ int girih_run(girih_plan_t plan, void* buf0, void* buf1, const void* const* coef
 /* Auto-tuner (paper, Section "Auto-tuning").  Allocates and initialises its
  * own arrays of the plan's grid (freed before return), times candidates with
  * HIP events on hip_stream, and writes the best parameters into *best and
- * the plan.  Test length: multiples of diamond rows, doubled until two
- * consecutive measurements agree within 3 % or max_seconds is spent.
+ * the plan.  A candidate is timed on the problem itself: back-to-back runs of
+ * the plan's T-step schedule (every diamond row, the clipped first and last
+ * rows included), the number of runs doubled while a measurement lasts less
+ * than 50 ms, until two consecutive measurements agree within 3 %
+ * (girih_adaptive_time) or the candidate's share of max_seconds is spent.
  *  mode: GIRIH_TUNE_EXHAUSTIVE  every feasible candidate
  *        GIRIH_TUNE_HILLCLIMB   per thread shape, local search over Dw and
  *                               the x tile (the paper's search)
  *        GIRIH_TUNE_MODEL       only the candidates given by
  *                               girih_tune_set_candidates (e.g. the top-k of
  *                               a learned cost model), in that order
- *  T: steps the tuned run will take (part of the problem).  Each measured
- *  candidate is appended to the plan's log (girih_tune_log). */
+ *  T: steps the tuned run will take (part of the problem, >= 1; 0 gives
+ *  GIRIH_E_INVALID).  Each measured candidate is appended to the plan's log
+ *  (girih_tune_log); GIRIH_E_UNSUPPORTED if no candidate ran. */
 #define GIRIH_TUNE_EXHAUSTIVE 0
 #define GIRIH_TUNE_HILLCLIMB 1
 #define GIRIH_TUNE_MODEL 2
 int girih_tune(girih_plan_t plan, int32_t mode, int64_t T, double max_seconds, void* hip_stream,
                girih_params* best, double* best_glups);
+
+/* The tuner's search and its adaptive test length with a caller-supplied
+ * measurement: the same code girih_tune runs, for other measurement backends
+ * (a cost model, another device, a recorded table) and for testing the
+ * search without a GPU.  Neither touches the device.
+ *
+ * girih_tune_search: measure(candidate, ctx) returns GLUP/s (<= 0: the
+ * candidate failed).  mode GIRIH_TUNE_EXHAUSTIVE or GIRIH_TUNE_MODEL measures
+ * the list in order until max_seconds is spent (at least one); HILLCLIMB
+ * searches per thread shape (threads_x, cells_per_lane) from the median
+ * diamond width and widest x tile of the smallest wavefront depth, moving to
+ * the best improving neighbour (next diamond width or wavefront depth up or
+ * down, at its widest x tile; next x tile up or down) until none improves.
+ * Every candidate is measured at most once.  Outputs: *best_index into cands
+ * (-1 if none measured > 0), *best_glups, *n_measured (any may be NULL).
+ * GIRIH_E_UNSUPPORTED if no candidate measured > 0.
+ *
+ * girih_adaptive_time: time_fn(reps, ctx) returns the seconds of reps
+ * back-to-back runs (negative: failure, GIRIH_E_HIP).  reps starts at 1 and
+ * doubles while a measurement is shorter than min_seconds; the per-run time
+ * is accepted when two consecutive measurements agree within tol (relative),
+ * or after max_seconds or max_tries measurements (the last one is taken). */
+typedef double (*girih_measure_fn)(const girih_params* candidate, void* ctx);
+typedef double (*girih_time_fn)(int64_t reps, void* ctx);
+int girih_tune_search(const girih_params* cands, int32_t n, int32_t mode, girih_measure_fn measure, void* ctx,
+                      double max_seconds, int32_t* best_index, double* best_glups, int32_t* n_measured);
+int girih_adaptive_time(girih_time_fn time_fn, void* ctx, double tol, double min_seconds, double max_seconds,
+                        int32_t max_tries, double* seconds_per_run, int64_t* reps, int32_t* tries);
 
 /* Candidate list for GIRIH_TUNE_MODEL (copied).  n <= 4096. */
 int girih_tune_set_candidates(girih_plan_t plan, const girih_params* cands, int32_t n);
@@ -173,10 +205,12 @@ typedef struct girih_tune_record {
 /* Copy up to cap records of the plan's tuner log; *n = total count. */
 int girih_tune_log(girih_plan_t plan, girih_tune_record* out, int32_t cap, int32_t* n);
 
-/* Resolved parameters, LDS bytes per workgroup, and the modelled blocked
- * code balance in bytes per lattice update (paper, Section "Memory traffic
- * model", scaled to the element size and including the redundant x-halo
- * reads of the chunking; for NAIVE the streaming (2 + n_coef) * size). */
+/* Resolved parameters, LDS bytes per workgroup, and the algorithmic code
+ * balance in bytes per lattice update: for MWD the paper's blocked code
+ * balance B_C (Section "Memory traffic model", both equations, scaled to the
+ * element size: 2 * size * R * [(2Dw - 2R) + (N_D*Dw + 2R)] / Dw^2, with N_D
+ * the domain-sized streams); the redundant x-halo that x-chunking reads on
+ * top of it is not included; for NAIVE the streaming (2 + n_coef) * size. */
 int girih_plan_info(girih_plan_t plan, girih_params* params, int64_t* lds_bytes, double* model_bytes_per_lup);
 
 /* Change the parameters of an existing plan (validated like girih_plan). */

@@ -157,8 +157,14 @@ const KernelEntry* find_naive(int st, int dt, int variant, int rows) {
 
 // Default MWD shape per radius and element size (diamond width, cells per
 // lane, waves along x); the tuner replaces it per problem.
-void default_mwd(int R, int dtype, int& dw, int& vx, int& wx) {
-    if (R == 1) {
+void default_mwd(int stencil, int R, int dtype, int& dw, int& vx, int& wx) {
+    if (kNCoef[stencil] > 0) {
+        // variable coefficients: the per-slot coefficient offsets take the
+        // registers a wider diamond would need
+        dw = dtype == GIRIH_F32 ? (R == 1 ? 12 : 16) : 8;
+        vx = 1;
+        wx = R == 1 || dtype == GIRIH_F64 ? 2 : 1;
+    } else if (R == 1) {
         dw = 12;
         vx = 1;
         wx = 2;
@@ -199,7 +205,7 @@ int resolve(girih_plan_s* p, const girih_params* in) {
     if (p->algo == GIRIH_MWD) {
         int dw = q.diamond_width, vx = q.cells_per_lane, wx = q.threads_x ? q.threads_x / 64 : 0;
         int ddw, dvx, dwx;
-        default_mwd(R, p->dtype, ddw, dvx, dwx);
+        default_mwd(p->stencil, R, p->dtype, ddw, dvx, dwx);
         if (q.threads_x < 0 || q.threads_x % 64 || vx < 0) return GIRIH_E_INVALID;
         if (dw == 0) dw = ddw;
         if (vx == 0 && wx == 0) { vx = dvx; wx = dwx; }
@@ -488,49 +494,194 @@ int alloc_tune_bufs(girih_plan_s* p, TuneBufs& b, hipStream_t s) {
 
 int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s);
 
-// Time one candidate: runs of k diamond rows (k*H steps for MWD, k*8 steps
-// naive), k doubling until two consecutive rates agree within 3 %.
-int measure(girih_plan_s* p, TuneBufs& b, hipStream_t s, double max_seconds, girih_tune_record& rec) {
-    const int64_t H = p->algo == GIRIH_MWD ? p->params.diamond_width / (2 * p->R) : 8;
-    const double lups_per_step = (double)p->grid.nx * p->grid.ny * p->grid.nz;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    const void* const* coefs = b.coef.empty() ? nullptr : (const void* const*)b.coef.data();
-    // warm-up (also allocates the scratch pair)
-    int rc = run_any(p, b.f[0], b.f[1], coefs, H, s);
-    if (rc) { hipEventDestroy(e0); hipEventDestroy(e1); return rc; }
-    double prev = -1, rate = 0, secs = 0;
-    int64_t rows = 2, steps = 0;
-    int reps = 0;
+// Adaptive test length (paper, Section "Auto-tuning": test runs are
+// lengthened until the measurement is stable).  time_reps(k) returns the
+// seconds of k back-to-back runs of the problem (negative: failure).  The
+// repeat count k doubles while a measurement is shorter than min_seconds;
+// the per-run time is accepted when two consecutive measurements agree
+// within tol (relative), or when max_seconds or max_tries is reached (the
+// last measurement is then taken).
+struct Adapted {
+    double per_run = 0;   // seconds per run of the accepted measurement
+    int64_t reps = 0;     // runs in it
+    int tries = 0;        // measurements taken
+    int status = GIRIH_OK;
+};
+
+template <class F>
+Adapted adaptive_time(F&& time_reps, double tol, double min_seconds, double max_seconds, int max_tries) {
+    Adapted r;
+    int64_t reps = 1;
+    double prev = -1;
     const double t0 = now_s();
     for (;;) {
-        steps = rows * H;
-        HIPCHK(hipEventRecord(e0, s));
-        rc = run_any(p, b.f[0], b.f[1], coefs, steps, s);
-        if (rc) break;
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        secs = ms * 1e-3;
-        rate = lups_per_step * steps / secs * 1e-9;
-        ++reps;
-        if (prev > 0 && std::fabs(rate - prev) <= 0.03 * std::max(rate, prev)) break;
-        if (now_s() - t0 > max_seconds || reps >= 12) break;
-        prev = rate;
-        if (secs < 0.05) rows *= 2;   // grow until a run is long enough to be stable
+        const double secs = time_reps(reps);
+        if (!(secs >= 0)) {
+            r.status = GIRIH_E_HIP;
+            return r;
+        }
+        ++r.tries;
+        const double per = secs / (double)reps;
+        r.per_run = per;
+        r.reps = reps;
+        if (prev > 0 && std::fabs(per - prev) <= tol * std::max(per, prev)) break;
+        if (now_s() - t0 > max_seconds || r.tries >= max_tries) break;
+        prev = per;
+        if (secs < min_seconds) reps *= 2;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    return r;
+}
+
+// Time one candidate on the problem it is tuned for: back-to-back runs of the
+// plan's own T-step schedule (every diamond row, the clipped first and last
+// rows included), with the adaptive length above (3 %, runs of at least
+// 50 ms).
+int measure(girih_plan_s* p, TuneBufs& b, hipStream_t s, int64_t T, double max_seconds, girih_tune_record& rec) {
+    const double lups = (double)p->grid.nx * p->grid.ny * p->grid.nz * (double)T;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return GIRIH_E_HIP;
+    }
+    const void* const* coefs = b.coef.empty() ? nullptr : (const void* const*)b.coef.data();
+    // warm-up (also allocates the scratch pair)
+    int rc = run_any(p, b.f[0], b.f[1], coefs, T, s);
+    if (rc == GIRIH_OK && hipStreamSynchronize(s) != hipSuccess) rc = GIRIH_E_HIP;
+    Adapted ad;
+    if (rc == GIRIH_OK) {
+        ad = adaptive_time(
+            [&](int64_t reps) -> double {
+                if (hipEventRecord(e0, s) != hipSuccess) return -1;
+                for (int64_t i = 0; i < reps; ++i) {
+                    rc = run_any(p, b.f[0], b.f[1], coefs, T, s);
+                    if (rc) return -1;
+                }
+                float ms = 0;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    return -1;
+                return ms * 1e-3;
+            },
+            0.03, 0.05, max_seconds, 12);
+        if (rc == GIRIH_OK) rc = ad.status;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     rec.params = p->params;
     rec.lds_bytes = p->kern->lds_bytes;
-    rec.steps = steps;
-    rec.seconds = secs;
-    rec.glups = rate;
-    rec.repeats = reps;
+    rec.steps = T * ad.reps;
+    rec.seconds = ad.per_run * (double)ad.reps;
+    rec.glups = rc == GIRIH_OK && ad.per_run > 0 ? lups / ad.per_run * 1e-9 : 0;
+    rec.repeats = ad.tries;
     rec.status = rc;
     return rc;
+}
+
+// The tuner's search over a candidate list, with any measurement
+// (measure(i) -> GLUP/s of candidate i, <= 0 when it fails).
+//  exhaustive (and model): every candidate in list order until max_seconds
+//  is spent (at least one);
+//  hill climbing (paper, Section "Auto-tuning"): per thread shape (waves
+//  along x and cells per lane), start at the median diamond width and the
+//  widest x tile of the smallest wavefront depth and move to the best
+//  improving neighbour until none improves: the next diamond width or
+//  wavefront depth up or down (at the widest x tile there), or the next x
+//  tile up or down at the same width and depth.
+// Returns the index of the best candidate (-1 if none measured).
+template <class M>
+int tune_search(const std::vector<girih_params>& cands, int mode, M&& measure_i, double max_seconds,
+                double& best_rate, int& n_measured) {
+    const double t_start = now_s();
+    std::vector<double> rate(cands.size(), -1.0);
+    best_rate = -1;
+    n_measured = 0;
+    int best_i = -1;
+    auto eval = [&](int i) -> double {
+        if (rate[i] < 0) {
+            const double r = measure_i(i);
+            rate[i] = r > 0 ? r : 0;
+            ++n_measured;
+            if (rate[i] > best_rate) {
+                best_rate = rate[i];
+                best_i = i;
+            }
+        }
+        return rate[i];
+    };
+    if (mode != GIRIH_TUNE_HILLCLIMB) {
+        for (size_t i = 0; i < cands.size(); ++i) {
+            if (n_measured > 0 && now_s() - t_start > max_seconds) break;
+            eval((int)i);
+        }
+        return best_rate > 0 ? best_i : -1;
+    }
+    std::map<std::pair<int, int>, std::vector<int>> by_shape;
+    for (size_t i = 0; i < cands.size(); ++i)
+        by_shape[{cands[i].threads_x, cands[i].cells_per_lane}].push_back((int)i);
+    for (auto& kv : by_shape) {
+        const std::vector<int>& g = kv.second;
+        std::vector<int> dws, nfs;
+        for (int i : g) {
+            dws.push_back(cands[i].diamond_width);
+            nfs.push_back(std::max(1, cands[i].wavefront_depth));
+        }
+        std::sort(dws.begin(), dws.end());
+        dws.erase(std::unique(dws.begin(), dws.end()), dws.end());
+        std::sort(nfs.begin(), nfs.end());
+        nfs.erase(std::unique(nfs.begin(), nfs.end()), nfs.end());
+        auto nf_of = [&](int i) { return std::max(1, cands[i].wavefront_depth); };
+        // candidates of one (diamond width, depth), by x tile
+        auto tiles = [&](int dw, int nf) {
+            std::vector<int> t;
+            for (int i : g)
+                if (cands[i].diamond_width == dw && nf_of(i) == nf) t.push_back(i);
+            std::sort(t.begin(), t.end(), [&](int a, int b) { return cands[a].tile_x < cands[b].tile_x; });
+            return t;
+        };
+        // start: median width (with a candidate at the smallest depth), widest tile
+        int cur = -1;
+        for (size_t d = dws.size() / 2, n = 0; n < dws.size() && cur < 0; ++n) {
+            const size_t di = (d + n) % dws.size();
+            for (int nf : nfs) {
+                auto t = tiles(dws[di], nf);
+                if (!t.empty()) { cur = t.back(); break; }
+            }
+        }
+        if (cur < 0) continue;
+        double cv = eval(cur);
+        for (int guard = 0; guard < 256; ++guard) {
+            if (now_s() - t_start > max_seconds) break;
+            const int dw = cands[cur].diamond_width, nf = nf_of(cur);
+            const int di = (int)(std::find(dws.begin(), dws.end(), dw) - dws.begin());
+            const int fi = (int)(std::find(nfs.begin(), nfs.end(), nf) - nfs.begin());
+            std::vector<int> nb;
+            for (int d : {-1, 1}) {
+                if (di + d >= 0 && di + d < (int)dws.size()) {
+                    auto t = tiles(dws[di + d], nf);
+                    if (!t.empty()) nb.push_back(t.back());
+                }
+                if (fi + d >= 0 && fi + d < (int)nfs.size()) {
+                    auto t = tiles(dw, nfs[fi + d]);
+                    if (!t.empty()) nb.push_back(t.back());
+                }
+            }
+            auto t = tiles(dw, nf);
+            const int ti = (int)(std::find(t.begin(), t.end(), cur) - t.begin());
+            if (ti > 0) nb.push_back(t[ti - 1]);
+            if (ti + 1 < (int)t.size()) nb.push_back(t[ti + 1]);
+            int bi = cur;
+            double bv = cv;
+            for (int i : nb) {
+                const double r = eval(i);
+                if (r > bv) { bv = r; bi = i; }
+            }
+            if (bi == cur) break;
+            cur = bi;
+            cv = bv;
+        }
+    }
+    return best_rate > 0 ? best_i : -1;
 }
 
 std::vector<girih_params> mwd_candidates(const girih_plan_s* p) {
@@ -683,9 +834,8 @@ int girih_candidates(girih_plan_t p, girih_params* out, int32_t cap, int32_t* n)
 
 int girih_tune(girih_plan_t p, int32_t mode, int64_t T, double max_seconds, void* hip_stream, girih_params* best,
                double* best_glups) {
-    if (!p || T < 0 || !(max_seconds > 0)) return GIRIH_E_INVALID;
+    if (!p || T < 1 || !(max_seconds > 0)) return GIRIH_E_INVALID;
     if (mode < 0 || mode > 2) return GIRIH_E_INVALID;
-    (void)T;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     std::vector<girih_params> cands;
     if (mode == GIRIH_TUNE_MODEL) cands = p->tuning.model_cands;
@@ -702,95 +852,60 @@ int girih_tune(girih_plan_t p, int32_t mode, int64_t T, double max_seconds, void
     TuneBufs bufs;
     int rc = alloc_tune_bufs(p, bufs, s);
     if (rc) return rc;
-    const double t_start = now_s();
     const double per_cand = std::max(0.05, std::min(2.0, max_seconds / std::max<size_t>(cands.size(), 1)));
-    std::map<std::vector<int32_t>, double> seen;
-    auto key = [](const girih_params& q) {
-        return std::vector<int32_t>{q.diamond_width, q.tile_x, q.threads_x, q.threads_y, q.tile_z, q.cells_per_lane};
-    };
+    std::vector<girih_params> resolved(cands.size());
     double best_rate = -1;
-    girih_params best_p = saved;
-    auto eval = [&](const girih_params& q) -> double {
-        auto it = seen.find(key(q));
-        if (it != seen.end()) return it->second;
-        girih_tune_record rec{};
-        rec.params = q;
-        int r2 = girih_plan_set_params(p, &q);
-        if (r2 == GIRIH_OK) r2 = measure(p, bufs, s, per_cand, rec);
-        rec.status = r2;
-        if (r2 != GIRIH_OK) {
-            (void)hipGetLastError();
-            rec.glups = 0;
-        }
-        p->tuning.log.push_back(rec);
-        seen[key(q)] = rec.glups;
-        if (rec.glups > best_rate) {
-            best_rate = rec.glups;
-            best_p = p->params;
-        }
-        return rec.glups;
-    };
-    if (mode == GIRIH_TUNE_HILLCLIMB && p->algo == GIRIH_MWD) {
-        // per thread shape (cells per lane), local search over (Dw, x tile)
-        std::map<int, std::vector<girih_params>> by_shape;
-        for (const auto& q : cands) by_shape[q.threads_x * 8 + q.cells_per_lane].push_back(q);
-        for (auto& kv : by_shape) {
-            auto& v = kv.second;
-            std::vector<int> dws;
-            for (auto& q : v) dws.push_back(q.diamond_width);
-            std::sort(dws.begin(), dws.end());
-            dws.erase(std::unique(dws.begin(), dws.end()), dws.end());
-            auto tiles_of = [&](int dw) {
-                std::vector<int> t;
-                for (auto& q : v)
-                    if (q.diamond_width == dw) t.push_back(q.tile_x);
-                std::sort(t.begin(), t.end());
-                return t;
-            };
-            auto make = [&](int dw, int tx) {
-                for (auto& q : v)
-                    if (q.diamond_width == dw && q.tile_x == tx) return q;
-                return v[0];
-            };
-            // start: median diamond width, widest tile
-            int di = (int)dws.size() / 2;
-            auto ts = tiles_of(dws[di]);
-            int ti = (int)ts.size() - 1;
-            double cur = eval(make(dws[di], ts[ti]));
-            for (int guard = 0; guard < 64 && now_s() - t_start < max_seconds; ++guard) {
-                int bd = di, bt = ti;
-                double bv = cur;
-                const int moves[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
-                for (auto& m : moves) {
-                    const int nd = di + m[0];
-                    if (nd < 0 || nd >= (int)dws.size()) continue;
-                    auto nts = tiles_of(dws[nd]);
-                    int nt = m[0] ? (int)nts.size() - 1 : ti + m[1];
-                    if (nt < 0 || nt >= (int)nts.size()) continue;
-                    const double r = eval(make(dws[nd], nts[nt]));
-                    if (r > bv) { bv = r; bd = nd; bt = nt; }
-                }
-                if (bd == di && bt == ti) break;
-                di = bd;
-                ti = bt;
-                cur = bv;
+    int n_measured = 0;
+    const int bi = tune_search(
+        cands, p->algo == GIRIH_MWD ? mode : GIRIH_TUNE_EXHAUSTIVE,
+        [&](int i) -> double {
+            girih_tune_record rec{};
+            rec.params = cands[i];
+            int r2 = girih_plan_set_params(p, &cands[i]);
+            if (r2 == GIRIH_OK) r2 = measure(p, bufs, s, T, per_cand, rec);
+            rec.status = r2;
+            if (r2 != GIRIH_OK) {
+                (void)hipGetLastError();
+                rec.glups = 0;
             }
-        }
-    } else {
-        for (const auto& q : cands) {
-            if (now_s() - t_start > max_seconds && best_rate > 0) break;
-            eval(q);
-        }
-    }
-    if (best_rate <= 0) {
+            resolved[i] = p->params;
+            p->tuning.log.push_back(rec);
+            return rec.glups;
+        },
+        max_seconds, best_rate, n_measured);
+    if (bi < 0) {
         (void)girih_plan_set_params(p, &saved);
         return GIRIH_E_UNSUPPORTED;
     }
-    rc = girih_plan_set_params(p, &best_p);
+    rc = girih_plan_set_params(p, &resolved[bi]);
     if (rc) return rc;
     if (best) *best = p->params;
     if (best_glups) *best_glups = best_rate;
     return GIRIH_OK;
+}
+
+int girih_tune_search(const girih_params* cands, int32_t n, int32_t mode, girih_measure_fn measure_fn, void* ctx,
+                      double max_seconds, int32_t* best_index, double* best_glups, int32_t* n_measured) {
+    if (!cands || n < 1 || !measure_fn || !(max_seconds > 0) || mode < 0 || mode > 2) return GIRIH_E_INVALID;
+    std::vector<girih_params> c(cands, cands + n);
+    double best = -1;
+    int nm = 0;
+    const int bi = tune_search(c, mode, [&](int i) { return measure_fn(&c[i], ctx); }, max_seconds, best, nm);
+    if (best_index) *best_index = bi;
+    if (best_glups) *best_glups = best;
+    if (n_measured) *n_measured = nm;
+    return bi < 0 ? GIRIH_E_UNSUPPORTED : GIRIH_OK;
+}
+
+int girih_adaptive_time(girih_time_fn time_fn, void* ctx, double tol, double min_seconds, double max_seconds,
+                        int32_t max_tries, double* seconds_per_run, int64_t* reps, int32_t* tries) {
+    if (!time_fn || !(tol >= 0) || !(max_seconds > 0) || max_tries < 1) return GIRIH_E_INVALID;
+    const Adapted a = adaptive_time([&](int64_t k) { return time_fn(k, ctx); }, tol, min_seconds, max_seconds,
+                                    max_tries);
+    if (seconds_per_run) *seconds_per_run = a.per_run;
+    if (reps) *reps = a.reps;
+    if (tries) *tries = a.tries;
+    return a.status;
 }
 
 int girih_tune_log(girih_plan_t p, girih_tune_record* out, int32_t cap, int32_t* n) {
@@ -811,12 +926,9 @@ int girih_plan_info(girih_plan_t p, girih_params* params, int64_t* lds_bytes, do
         if (p->algo == GIRIH_NAIVE) {
             *model_bytes_per_lup = ND * s;
         } else {
-            // paper's B_C in words: R*[(2Dw-2R) + (N_D*Dw+2R)] * 2 / Dw^2, the read
-            // term widened by the redundant x-halo of the chunk
+            // paper's B_C in words: R*[(2Dw-2R) + (N_D*Dw+2R)] * 2 / Dw^2
             const double Dw = p->params.diamond_width, R = p->R;
-            const double L = Dw / R, hx = R * (L - 1);
-            const double rho = ((double)p->x_own + 2 * hx) / (double)p->x_own;
-            *model_bytes_per_lup = 2 * s * R * ((2 * Dw - 2 * R) + rho * (ND * Dw + 2 * R)) / (Dw * Dw);
+            *model_bytes_per_lup = 2 * s * R * ((2 * Dw - 2 * R) + (ND * Dw + 2 * R)) / (Dw * Dw);
         }
     }
     return GIRIH_OK;

@@ -57,6 +57,9 @@ class GirihError(RuntimeError):
 
 _LIB = None
 
+MEASURE_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(GirihParams), ctypes.c_void_p)
+TIME_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_int64, ctypes.c_void_p)
+
 # name -> (restype, argtypes): the exported symbols of include/girih.h
 SIGNATURES = {
     "girih_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
@@ -68,6 +71,12 @@ SIGNATURES = {
     "girih_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                   ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.POINTER(ctypes.c_double)]),
     "girih_tune_set_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.c_int32]),
+    "girih_tune_search": (ctypes.c_int, [ctypes.POINTER(GirihParams), ctypes.c_int32, ctypes.c_int32, MEASURE_FN,
+                                         ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
+    "girih_adaptive_time": (ctypes.c_int, [TIME_FN, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "girih_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32)]),
     "girih_tune_log": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihTuneRecord), ctypes.c_int32,
@@ -165,6 +174,32 @@ def girih_tune(plan, mode, T, max_seconds, stream_ptr):
                            ctypes.byref(best), ctypes.byref(g))
     _check(rc, "girih_tune")
     return best.as_dict(), g.value
+
+
+def girih_tune_search(cands, mode, measure, max_seconds=1e9):
+    """The tuner's search over `cands` (dicts) with a Python measurement
+    measure(params_dict) -> GLUP/s; returns (best index, best GLUP/s, number
+    of candidates measured)."""
+    arr = (GirihParams * max(len(cands), 1))(*[GirihParams.from_dict(c) for c in cands])
+    cb = MEASURE_FN(lambda p, ctx: float(measure(p.contents.as_dict())))
+    bi, bg, nm = ctypes.c_int32(-1), ctypes.c_double(0), ctypes.c_int32(0)
+    rc = _lib().girih_tune_search(arr, len(cands), TUNE_MODES[mode] if isinstance(mode, str) else int(mode), cb,
+                                  None, float(max_seconds), ctypes.byref(bi), ctypes.byref(bg), ctypes.byref(nm))
+    if rc != E_UNSUPPORTED:
+        _check(rc, "girih_tune_search")
+    return bi.value, bg.value, nm.value
+
+
+def girih_adaptive_time(time_reps, tol=0.03, min_seconds=0.05, max_seconds=1e9, max_tries=12):
+    """The tuner's adaptive test length with a Python timer time_reps(reps) ->
+    seconds; returns (seconds per run, reps of the accepted measurement,
+    measurements taken)."""
+    cb = TIME_FN(lambda k, ctx: float(time_reps(int(k))))
+    per, reps, tries = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(_lib().girih_adaptive_time(cb, None, float(tol), float(min_seconds), float(max_seconds), int(max_tries),
+                                      ctypes.byref(per), ctypes.byref(reps), ctypes.byref(tries)),
+           "girih_adaptive_time")
+    return per.value, reps.value, tries.value
 
 
 def girih_tune_set_candidates(plan, cands):
