@@ -11,16 +11,26 @@ device synchronisation.
 
 Beside the headline value the line carries:
   roofline      the dominant kernel (the diamond-row kernel) against HBM
-                peak: algorithmic bytes per launch (the blocked code balance
-                of the plan, bytes per lattice update, times the updates of one
-                launch) divided by its average launch duration, measured with
-                HIP events on the launch stream inside the timed runs; traffic
-                from the committed rocprofv3 counter summary when it was taken
-                on the current kernel source, else null;
+                peak: algorithmic bytes per launch (the paper's blocked code
+                balance B_C of the plan, bytes per lattice update, times the
+                updates of one launch) divided by its average launch duration,
+                measured with HIP events on the launch stream inside the timed
+                runs; the redundant x-halo reads of the x-chunking are reported
+                apart (x_halo_read_factor), and traffic comes from the committed
+                rocprofv3 counter summary when it was taken on the current
+                kernel source, else null;
   cpu_baseline  the FP64 CPU oracle on the same workload, a bounded number of
-                steps, on the host's cores (and on one thread);
+                steps, on the host's cores (and on one thread), with the host's
+                CPU model, sockets, memory and compiler; and the oracle on the
+                other workloads for a few seconds each;
   compare       naive GPU sweep (FP64), blocked FP32 run and its error against
-                the FP64 result, measured outside the timed region.
+                the FP64 result, measured outside the timed region;
+  per_stencil   every other workload of the study (25-point constant 512^3,
+                25-point variable 384^3, 7-point variable 256x512x1024), blocked
+                and naive, FP64 and FP32, timed the same way outside the timed
+                region, with the FP32 error against the FP64 blocked result
+                (which equals the FP64 oracle bit for bit, as the GPU parity
+                tests check).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -79,6 +89,142 @@ def launch_lups(nx, ny, nz, T, H):
     return out
 
 
+def x_halo_factor(q, R):
+    """Cells an x chunk reads per cell it owns: the owned tile plus the
+    redundant halo of R*(L-1) cells per side that the chunk recomputes."""
+    L = q["diamond_width"] // R
+    return (q["tile_x"] + 2 * R * (L - 1)) / q["tile_x"]
+
+
+def host_info():
+    """CPU model, sockets, logical CPUs, memory and C compiler of this host."""
+    import platform
+    import subprocess
+    model, sockets = platform.processor() or "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                if k.strip() == "model name":
+                    model = v.strip()
+                elif k.strip() == "physical id":
+                    sockets.add(v.strip())
+    except OSError:
+        pass
+    mem_gb = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+    except OSError:
+        pass
+    try:
+        cc = subprocess.run(["gcc", "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        cc = "unknown"
+    return {"cpu_model": model, "sockets": max(1, len(sockets)), "logical_cpus": os.cpu_count(),
+            "mem_gib": mem_gb, "compiler": cc + " -O2 -ffp-contract=off -fopenmp"}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_runs(sw, g0, T, coefs, reps, torch):
+    """Median seconds of `reps` runs of a plan from a fresh copy of g0 (HIP
+    events on the current stream; the copies are outside the events)."""
+    stream = torch.cuda.current_stream()
+    b0, b1 = g0.clone(), g0.clone()
+    sw.run(b0, b1, T, coefs)   # warm-up
+    times = []
+    for _ in range(reps):
+        b0.copy_(g0)
+        b1.copy_(g0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = sw.run(b0, b1, T, coefs)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    return sorted(times)[len(times) // 2], out
+
+
+def per_stencil(torch, dev, reps=3):
+    """The other workloads, blocked and naive, FP64 and FP32 (default plans)."""
+    import numpy as np
+    import paper_1510_04995_amd as P
+    from workloads import WORKLOADS, field_and_coefs
+    res = {}
+    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024"):
+        w = WORKLOADS[name]
+        h = w.radius
+        log("inputs " + name)
+        u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0)
+        consts = None if c is None else [float(x) for x in c]
+        entry = {"stencil": w.stencil, "grid": [w.nx, w.ny, w.nz], "T": w.T}
+        ref64 = None
+        for dtype in ("f64", "f32"):
+            npdt = np.float64 if dtype == "f64" else np.float32
+            g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
+            coefs = [] if arr is None else [torch.from_numpy(a.astype(npdt)).to(dev) for a in arr]
+            for algo in ("mwd", "naive"):
+                log("time %s %s %s" % (name, dtype, algo))
+                sw = P.Sweep(w.stencil, dtype, w.nx, w.ny, w.nz, consts, algo)
+                info = sw.info()
+                sec, out = time_runs(sw, g0, w.T, coefs, reps, torch)
+                key = "%s_%s" % (algo, dtype)
+                entry[key + "_glups"] = round(w.lups / sec / 1e9, 2)
+                entry[key + "_bytes_per_lup_alg"] = round(info["model_bytes_per_lup"], 3)
+                if algo == "mwd":
+                    p = info["params"]
+                    entry[key + "_plan"] = [p["diamond_width"], p["cells_per_lane"], p["threads_x"] // 64,
+                                            p["tile_x"]]
+                    if dtype == "f64":
+                        ref64 = out.clone()
+                    else:
+                        rel, mx, _ = P.error_norms(out, ref64, h, w.nx, w.ny, w.nz)
+                        entry["f32_rel_l2_vs_f64"] = float("%.3e" % rel)
+                        entry["f32_max_abs_vs_f64"] = float("%.3e" % mx)
+                else:
+                    ref = ref64 if dtype == "f64" else None
+                    if ref is not None:
+                        entry["mwd_vs_naive_f64_bitwise_diff"] = P.error_norms(out, ref, h, w.nx, w.ny, w.nz)[2]
+                sw.close()
+                del out
+            del g0, coefs
+            torch.cuda.empty_cache()
+        entry["mwd_vs_naive_f64"] = round(entry["mwd_f64_glups"] / entry["naive_f64_glups"], 3)
+        del ref64
+        torch.cuda.empty_cache()
+        res[name] = entry
+    return res
+
+
+def oracle_rates(O, seconds=4.0):
+    """The oracle on the other workloads: a few steps each on all threads."""
+    from workloads import WORKLOADS, field_and_coefs
+    out = {}
+    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024"):
+        w = WORKLOADS[name]
+        log("oracle " + name)
+        u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0)
+        a0, a1 = u0.copy(), u0.copy()
+        t = time.perf_counter()
+        O.sweep(w.stencil, a0, a1, 1, c, arr)
+        one = time.perf_counter() - t
+        steps = int(max(1, min(w.T, seconds / max(one, 1e-3))))
+        a0, a1 = u0.copy(), u0.copy()
+        t = time.perf_counter()
+        O.sweep(w.stencil, a0, a1, steps, c, arr)
+        dt = time.perf_counter() - t
+        out[name] = {"glups": round(w.nx * w.ny * w.nz * steps / dt / 1e9, 4),
+                     "sample": "%d of %d steps, %.1f s" % (steps, w.T, dt)}
+        del a0, a1, u0, arr
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +233,7 @@ def main():
     ap.add_argument("--params", default=None, help="JSON dict of girih_params fields for the blocked plan")
     ap.add_argument("--no-compare", action="store_true", help="skip the naive / FP32 comparison runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-suite", action="store_true", help="skip the other workloads (per_stencil)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -147,7 +294,7 @@ def main():
     q = info["params"]
     H = q["diamond_width"] // (2 * h)
     per_launch = launch_lups(w.nx, w.ny, w.nz, w.T, H)
-    bpl = info["model_bytes_per_lup"]
+    bpl = info["model_bytes_per_lup"]   # the paper's B_C for this plan
     alg_bytes_per_launch = bpl * sum(per_launch) / len(per_launch)
     avg_launch_s = kern_ms / max(n_launch, 1) * 1e-3
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
@@ -161,7 +308,9 @@ def main():
             traffic = prof.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "mwd_row_kernel", "bytes_per_lup_model": round(bpl, 3),
+                "kernel": "mwd_row_kernel", "bytes_per_lup_alg": round(bpl, 3),
+                "x_halo_read_factor": round(x_halo_factor(q, h), 4),
+                "traffic_vs_alg": None if traffic is None else round(traffic / alg_bytes_per_launch, 3),
                 "lups_per_launch": round(sum(per_launch) / len(per_launch)), "launches": n_launch,
                 "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
 
@@ -210,6 +359,10 @@ def main():
         s32.close()
         del f0, f1, g32, m0, m1
 
+    sw_rest = None
+    if not args.no_suite:
+        sw_rest = per_stencil(torch, dev)
+
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -254,6 +407,9 @@ def main():
             O.set_num_threads(n_all)
         cpu["value_one_thread"] = round(w.nx * w.ny * w.nz * t1 / dt1 / 1e9, 4)
         cpu["sample_one_thread"] = "%d steps, %.1f s" % (t1, dt1)
+        cpu["host"] = host_info()
+        if not args.no_suite:
+            cpu["other_workloads"] = oracle_rates(O)
 
     out = {
         "metric": "GLUP/s per stencil at 1 GPU + % HBM roofline; blocked vs naive, FP32 vs FP64",
@@ -268,13 +424,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "stencil": "7-point constant (c0=0.4, c1=0.1)",
+        "config": {"workload": WORKLOAD, "stencil": "7-point constant (c0=0.4, c1=0.1)", "stencil_id": w.stencil,
                    "grid": [w.nx, w.ny, w.nz], "halo": h, "T": w.T, "algo": "mwd", "params": q,
                    "lds_bytes": info["lds_bytes"], "median_run_ms": round(sorted(times)[len(times) // 2] * 1e3, 3),
                    "kernel_source_hash": src_hash},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "compare": compare,
+        "per_stencil": sw_rest,
     }
     print(json.dumps(out), flush=True)
     sw.close()

@@ -35,15 +35,28 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(jobs=None, verbose=False):
-    """Compile all HIP sources and link the shared library; returns its path."""
+def _headers():
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    return [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")] + \
+        [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+
+
+def build(jobs=None, verbose=False, incremental=False):
+    """Compile all HIP sources and link the shared library; returns its path.
+
+    incremental: keep an object that is newer than its source and every
+    header (a development shortcut; the default recompiles everything)."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     srcs = sources()
     jobs = jobs or min(8, os.cpu_count() or 4)
+    newest_header = max(os.path.getmtime(h) for h in _headers())
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+        if incremental and os.path.exists(obj) and \
+                os.path.getmtime(obj) > max(newest_header, os.path.getmtime(src)):
+            return obj
         cmd = [hipcc] + CFLAGS + ["-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -64,4 +77,4 @@ def build(jobs=None, verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -71,13 +71,31 @@ template <class S, typename Real>
 void add_family(std::vector<KernelEntry>& t, int st, int dt) {
     add_naive<S, Real>(t, st, dt);
     constexpr bool F64 = sizeof(Real) == 8;
-    // The blocked sweep of the variable-coefficient stencils is not registered
-    // in this version (its coefficient loads are not yet validated on the
-    // device): GIRIH_MWD plans for them return GIRIH_E_UNSUPPORTED and the
-    // naive sweep serves these stencils.
     // The second-order-in-time stencil has a naive sweep only: its blocked
     // form needs a third time level per diamond cell.
-    if constexpr (S::NCOEF > 0 || S::LEAPFROG) {
+    if constexpr (S::LEAPFROG) {
+    } else if constexpr (S::NCOEF > 0 && S::R == 1) {
+        // Variable coefficients: every slot also holds the byte offset of its
+        // coefficient row, so fewer register slots fit than for the constant
+        // stencil (Dw = 12 spills in FP64).
+        add_mwd<S, Real, 8, 1, 2>(t, st, dt);
+        add_mwd<S, Real, 8, 2, 1>(t, st, dt);
+        if constexpr (F64) {
+            add_mwd<S, Real, 8, 1, 3>(t, st, dt);
+        } else {
+            add_mwd<S, Real, 8, 1, 4>(t, st, dt);
+            add_mwd<S, Real, 12, 1, 2>(t, st, dt);
+            add_mwd<S, Real, 12, 2, 1>(t, st, dt);
+            add_mwd<S, Real, 16, 1, 1>(t, st, dt);
+        }
+    } else if constexpr (S::NCOEF > 0) {
+        add_mwd<S, Real, 8, 1, 2>(t, st, dt);
+        add_mwd<S, Real, 8, 2, 1>(t, st, dt);
+        if constexpr (F64) {
+            add_mwd<S, Real, 8, 1, 1>(t, st, dt);
+        } else {
+            add_mwd<S, Real, 16, 1, 1>(t, st, dt);
+        }
     } else if constexpr (S::R == 1) {
         // (diamond width, cells per lane, waves along x)
         add_mwd<S, Real, 4, 2, 2>(t, st, dt);

@@ -299,8 +299,8 @@ enum : int {
 // does proportionally less work per step.  The host launches such a kernel
 // only for rows whose every wave fits (mwd_slots_needed).
 template <class S, typename Real, int DW, int VX, int WX, int NSV>
-__global__ void __launch_bounds__(64 * (DW / 2) * WX)
-mwd_row_kernel(MwdArgs<Real> a) {
+__device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk, const int diamond,
+                                         Real* __restrict__ stage) {
     using KK = MwdKernel<S, Real, DW, VX, WX>;
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
@@ -327,7 +327,6 @@ mwd_row_kernel(MwdArgs<Real> a) {
     constexpr bool CPF = NSV > 0;
     constexpr int SB = (int)sizeof(Real);
     static_assert(NS <= 32, "slot masks are 32-bit");
-    __shared__ Real stage[KK::LDS_ROWS * XLP];
 
     // ---- geometry (32-bit: sizes are bounded by the planner) ----------------
     const int nx = (int)a.g.nx, ny = (int)a.g.ny, nz = (int)a.g.nz, hh = a.g.h;
@@ -337,19 +336,6 @@ mwd_row_kernel(MwdArgs<Real> a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int pw = wave % KK::NPAIRS;              // row pair of this wave
     const int cb = 64 * VX * (wave / KK::NPAIRS);  // first column of this wave's x slice
-    // Workgroups are dealt to the XCDs round-robin in launch order and each
-    // XCD has its own L2.  Renumber so that every XCD takes one contiguous
-    // run of (diamond, x-chunk) tiles: the x chunks of a diamond, whose
-    // redundant halo columns overlap, and neighbouring diamonds, which share
-    // edge rows, then read those cells through the same L2.  (A bijection
-    // for any XCD count; the count only sets the locality.)
-    constexpr uint32_t NXCD = 8;
-    const uint32_t n_tiles = gridDim.x * gridDim.y;
-    const uint32_t launch_id = blockIdx.x + gridDim.x * blockIdx.y;
-    const uint32_t per_xcd = n_tiles / NXCD, extra = n_tiles % NXCD;
-    const uint32_t xcd = launch_id % NXCD, pos = launch_id / NXCD;
-    const uint32_t tile = (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
-    const int chunk = (int)(tile % gridDim.x), diamond = (int)(tile / gridDim.x);
     const int ybase = (int)(a.c_first + (int64_t)diamond * DW) - DW / 2;   // global y of local row 0
     const int x_own_lo = chunk * a.x_own;
     const int x_own_hi = x_own_lo + a.x_own < nx ? x_own_lo + a.x_own : nx;
@@ -998,6 +984,29 @@ mwd_row_kernel(MwdArgs<Real> a) {
         sweep(std::integral_constant<bool, true>{});
     else
         sweep(std::integral_constant<bool, false>{});
+}
+
+// Workgroups are dealt to the XCDs round-robin in launch order and each XCD
+// has its own L2.  Renumber so that every XCD takes one contiguous run of
+// (diamond, x-chunk) tiles: the x chunks of a diamond, whose redundant halo
+// columns overlap, and neighbouring diamonds, which share edge rows, then
+// read those cells through the same L2.  (A bijection for any XCD count; the
+// count only sets the locality.)
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t launch_id, uint32_t n_tiles) {
+    constexpr uint32_t NXCD = 8;
+    const uint32_t per_xcd = n_tiles / NXCD, extra = n_tiles % NXCD;
+    const uint32_t xcd = launch_id % NXCD, pos = launch_id / NXCD;
+    return (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
+}
+
+// One diamond row: one workgroup per (diamond, x-chunk) tile.
+template <class S, typename Real, int DW, int VX, int WX, int NSV>
+__global__ void __launch_bounds__(64 * (DW / 2) * WX)
+mwd_row_kernel(MwdArgs<Real> a) {
+    using KK = MwdKernel<S, Real, DW, VX, WX>;
+    __shared__ Real stage[KK::LDS_ROWS * KK::XLP];
+    const uint32_t tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    mwd_tile<S, Real, DW, VX, WX, NSV>(a, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage);
 }
 
 }  // namespace girih

@@ -29,6 +29,19 @@ FP64_PEAK_TFLOPS = 78.6
 LDS_BYTES_PER_CLK = 128
 
 
+STENCIL_CLASS = {"7c": "Stencil7C", "7v": "Stencil7V", "25c": "Stencil25C", "25v": "Stencil25V"}
+
+
+def _plan_key(b):
+    """The part of the diamond-row kernel's name that identifies the bench
+    line's plan (stencil, element type, diamond width, cells per lane, waves
+    along x), shared by its full and clipped-row instances."""
+    q = b["config"]["params"]
+    st = STENCIL_CLASS[b["config"].get("stencil_id", "7c")]
+    return "%s, %s, %d, %d, %d," % (st, "double" if b["dtype"] == "f64" else "float", q["diamond_width"],
+                                    q["cells_per_lane"], q["threads_x"] // 64)
+
+
 def _bench_line(path):
     with open(path) as f:
         for line in f:
@@ -56,8 +69,7 @@ def stats(csv_path, bench_path, out_path, command):
     # the plan's diamond-row kernels (full and clipped-row slot counts) together:
     # bench.py's per-launch average covers all of them
     q = b["config"]["params"]
-    key = "%s, %d, %d, %d," % ("double" if b["dtype"] == "f64" else "float", q["diamond_width"],
-                               q["cells_per_lane"], q["threads_x"] // 64)
+    key = _plan_key(b)
     mine = [r for r in rows if ROW_KERNEL in r["Name"] and key in r["Name"]]
     calls = sum(int(r["Calls"]) for r in mine)
     tot_ns = sum(float(r["TotalDurationNs"]) for r in mine)
@@ -106,7 +118,8 @@ def traffic(fetch_csv, write_csv, bench_path, copy_mib, out_path, command):
     rl = b["roofline"]
     if total:
         res["bytes_per_lup_measured"] = total / rl["lups_per_launch"]
-        res["bytes_per_lup_model"] = rl["bytes_per_lup_model"]
+        res["bytes_per_lup_alg"] = rl["bytes_per_lup_alg"]
+        res["x_halo_read_factor"] = rl.get("x_halo_read_factor")
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1)
         f.write("\n")
@@ -130,8 +143,7 @@ def _row_kernel_means(path, key):
 def core(path_a, path_b, bench_path, out_path, command):
     b = _bench_line(bench_path)
     q = b["config"]["params"]
-    key = "%s, %d, %d, %d," % ("double" if b["dtype"] == "f64" else "float", q["diamond_width"],
-                               q["cells_per_lane"], q["threads_x"] // 64)
+    key = _plan_key(b)
     m = _row_kernel_means(path_a, key)
     m.update({k: v for k, v in _row_kernel_means(path_b, key).items() if k not in m})
     cyc = m["GRBM_GUI_ACTIVE"] / N_XCD              # kernel cycles (the counter sums the XCDs)
@@ -169,8 +181,8 @@ def core(path_a, path_b, bench_path, out_path, command):
              "chip totals: %d CUs, %d SIMDs, %d XCDs." % (N_CU, N_SIMD, N_XCD), "",
              "| quantity | value |", "|---|---|"]
     lines += ["| %s | %s |" % r for r in rows]
-    lines += ["", "bench.py (same run): %.2f GLUP/s, %.1f %% of the HBM roofline at %.3f B/LUP (model)" % (
-        b["value"], 100 * rl["frac"], rl["bytes_per_lup_model"])]
+    lines += ["", "bench.py (same run): %.2f GLUP/s, %.1f %% of the HBM roofline at %.3f B/LUP (the paper's "
+              "B_C of the plan)" % (b["value"], 100 * rl["frac"], rl["bytes_per_lup_alg"])]
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -91,12 +91,20 @@ def test_plan_rejects_bad_tile_params():
     assert e.value.code == G.E_INVALID
 
 
-def test_mwd_variable_coefficients_unsupported():
-    for st, h in (("7v", 1), ("25v", 4)):
-        with pytest.raises(G.GirihError) as e:
-            G.girih_plan(st, "f64", grid(h=h), None, "mwd")
-        assert e.value.code == G.E_UNSUPPORTED
-        G.girih_destroy(G.girih_plan(st, "f64", grid(h=h), None, "naive"))
+def test_mwd_variable_coefficient_shapes():
+    """Blocked plans of the variable-coefficient stencils exist for the
+    registered (spill-free) shapes only; the second-order-in-time stencil has
+    none."""
+    for st, h, dt, dw in (("7v", 1, "f64", 8), ("7v", 1, "f32", 12), ("25v", 4, "f64", 8), ("25v", 4, "f32", 16)):
+        p = G.girih_plan(st, dt, grid(h=h), None, "mwd")
+        assert G.girih_plan_info(p)[0]["diamond_width"] == dw
+        G.girih_destroy(p)
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7v", "f64", grid(), None, "mwd", {"diamond_width": 12})     # spills: not compiled
+    assert e.value.code == G.E_UNSUPPORTED
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("25l", "f64", grid(h=4), (0.1, 0.1, 0.1, 0.1, 0.1), "mwd")
+    assert e.value.code == G.E_UNSUPPORTED
 
 
 def test_run_rejects_without_launch():
@@ -144,3 +152,21 @@ def test_leapfrog_plans():
     with pytest.raises(G.GirihError) as e:
         G.girih_plan("25l", "f64", g, None, "naive")          # constants are required
     assert e.value.code == G.E_INVALID
+
+
+@pytest.mark.parametrize("stencil,dtype", [("7c", "f64"), ("7c", "f32"), ("25c", "f64"), ("7v", "f64"), ("7v", "f32"),
+                                           ("25v", "f64"), ("25v", "f32")])
+def test_plan_info_reports_the_papers_code_balance(stencil, dtype):
+    """girih_plan_info gives the paper's B_C (Section "Memory traffic model")
+    of the plan's diamond width, scaled to the element size, with N_D the
+    field pair plus the coefficient arrays; every stencil and precision has
+    a default blocked plan."""
+    from oracle import models
+    R = 1 if stencil.startswith("7") else 4
+    nd = 2 + {"7c": 0, "7v": 7, "25c": 0, "25v": 13}[stencil]
+    cc = {"7c": (0.4, 0.1), "25c": (0.2, 0.05, 0.04, 0.03, 0.0133)}.get(stencil)
+    p = G.girih_plan(stencil, dtype, G.make_grid(96, 80, 40, R), cc, "mwd")
+    params, lds, bpl = G.girih_plan_info(p)
+    G.girih_destroy(p)
+    word = 8 if dtype == "f64" else 4
+    assert bpl == pytest.approx(models.code_balance(params["diamond_width"], R, nd, word_bytes=word), rel=1e-12)

@@ -67,7 +67,7 @@ def _bench_line(tmp_path):
     b = {"metric": "m", "value": 500.0, "dtype": "f64",
          "config": {"workload": "w", "kernel_source_hash": "h",
                     "params": {"diamond_width": 12, "tile_x": 106, "threads_x": 128, "cells_per_lane": 1}},
-         "roofline": {"frac": 0.4, "bytes_per_lup_model": 5.9, "launches": 12, "avg_launch_ms": 1.0}}
+         "roofline": {"frac": 0.4, "bytes_per_lup_alg": 5.33, "launches": 12, "avg_launch_ms": 1.0}}
     p = tmp_path / "bench.json"
     p.write_text(json.dumps(b) + "\n")
     return p
@@ -167,4 +167,5 @@ def test_tune_study_table(tmp_path):
     tune_study.summary(str(p), str(out), "cmd")
     t = out.read_text()
     assert "176 records; loss 26.9 -> 0.0009" in t
-    assert "| 7c f64 | 256x512x1024, 64 | 400.0 (28, 6.5 s) | 399.0 (15, 3.0 s) | 398.0 (5, 1.2 s) | 304.2 | 0.995 |" in t
+    assert ("| 7c f64 | 256x512x1024, 64 | 400.0 (28, 6.5 s) | 399.0 (15, 3.0 s) | 398.0 (5, 1.2 s) | 304.2 | 0.995 "
+            "| 0.997 |") in t
