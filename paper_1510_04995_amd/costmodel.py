@@ -113,7 +113,11 @@ class CostModel:
         X = np.asarray(X, dtype=np.float64)
         self.mean = X.mean(axis=0)
         sd = X.std(axis=0)
-        self.scale = np.where(sd > 1e-12, sd, 1.0)
+        # a feature with no spread in the training set carries no information
+        # the network could have learned: it standardises to 0 for every
+        # candidate (e.g. the number of coefficient arrays when training saw
+        # constant-coefficient stencils only)
+        self.scale = np.where(sd > 1e-12, sd, np.inf)
         x = torch.from_numpy(self._norm(X)).to(self.dev).contiguous()
         t = torch.from_numpy(np.log(np.asarray(glups, dtype=np.float64)).astype(np.float32)).to(self.dev)
         n = x.shape[0]

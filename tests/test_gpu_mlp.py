@@ -91,10 +91,12 @@ def test_training_fits_a_smooth_target():
 
 
 def test_model_proposals_reach_exhaustive_with_fewer_measurements():
-    """Train on the tuner's measurements of three small problems, then tune an
-    unseen grid: the model's top-5 must reach 90 % of exhaustive search's best
-    while measuring fewer candidates (and the paper's hill-climbing tuner is
-    reported beside it)."""
+    """Train on the tuner's measurements of three small constant-coefficient
+    problems, then tune an unseen problem -- the 7-point variable-coefficient
+    stencil, FP64 and FP32: the model's top-5 must reach 90 % of exhaustive
+    search's best while measuring fewer candidates than exhaustive search and
+    than the paper's hill-climbing tuner, at a rate no lower than hill
+    climbing's (within the 3 % measurement tolerance)."""
     import paper_1510_04995_amd as P
     from paper_1510_04995_amd import costmodel as C
     X, y = [], []
@@ -111,21 +113,23 @@ def test_model_proposals_reach_exhaustive_with_fewer_measurements():
     model = C.CostModel(seed=0)
     losses = model.fit(X, y, steps=2000)
     assert losses[-1] < losses[0]
-    nx, ny, nz, T = 128, 192, 256, 64
-    ex = P.Sweep("7c", "f64", nx, ny, nz, [0.4, 0.1], "mwd")
-    t0 = time.perf_counter()
-    _, best_exh = ex.tune("exhaustive", T, 30.0)
-    t_exh = time.perf_counter() - t0
-    n_exh = len(ex.tune_log())
-    t0 = time.perf_counter()
-    _, best_mlp, n_mlp = C.tune_with_model(ex, model, T, k=5)
-    t_mlp = time.perf_counter() - t0
-    hc = P.Sweep("7c", "f64", nx, ny, nz, [0.4, 0.1], "mwd")
-    _, best_hc = hc.tune("hillclimb", T, 30.0)
-    n_hc = len(hc.tune_log())
-    print("exhaustive %.1f GLUP/s (%d measured, %.1f s); model top-5 %.1f (%d, %.1f s); hill-climb %.1f (%d)"
-          % (best_exh, n_exh, t_exh, best_mlp, n_mlp, t_mlp, best_hc, n_hc), flush=True)
-    assert n_mlp <= 5 < n_exh
-    assert best_mlp >= 0.9 * best_exh
-    ex.close()
-    hc.close()
+    nx, ny, nz, T = 128, 192, 256, 32
+    for dt in ("f64", "f32"):
+        ex = P.Sweep("7v", dt, nx, ny, nz, None, "mwd")
+        t0 = time.perf_counter()
+        _, best_exh = ex.tune("exhaustive", T, 60.0)
+        t_exh = time.perf_counter() - t0
+        n_exh = len(ex.tune_log())
+        t0 = time.perf_counter()
+        _, best_mlp, n_mlp = C.tune_with_model(ex, model, T, k=5)
+        t_mlp = time.perf_counter() - t0
+        hc = P.Sweep("7v", dt, nx, ny, nz, None, "mwd")
+        _, best_hc = hc.tune("hillclimb", T, 60.0)
+        n_hc = len(hc.tune_log())
+        print("7v %s: exhaustive %.1f GLUP/s (%d measured, %.1f s); model top-5 %.1f (%d, %.1f s); "
+              "hill-climb %.1f (%d)" % (dt, best_exh, n_exh, t_exh, best_mlp, n_mlp, t_mlp, best_hc, n_hc), flush=True)
+        assert n_mlp <= 5 < n_exh
+        assert best_mlp >= 0.9 * best_exh
+        assert n_mlp < n_hc and best_mlp >= 0.97 * best_hc
+        ex.close()
+        hc.close()
