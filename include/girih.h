@@ -41,6 +41,7 @@ extern "C" {
 #define GIRIH_E_HIP (-4)         /* a HIP runtime call failed */
 #define GIRIH_E_NOMEM (-5)       /* device or host allocation failed */
 #define GIRIH_E_NOGPU (-6)       /* no usable gfx950 device */
+#define GIRIH_E_SCRATCH (-7)     /* grid larger than girih_run_noalloc's fixed scratch */
 
 /* Stencils (paper Listings 1-4; the 25-point constant stencil is the
  * first-order Jacobi form of Listing 3's bracketed term, the leapfrog one is
@@ -132,6 +133,25 @@ int girih_plan(girih_plan_t* out, girih_stencil stencil, girih_dtype dtype, cons
  *  the first run (GIRIH_E_NOMEM if that fails) and freed by girih_destroy. */
 int girih_run(girih_plan_t plan, void* buf0, void* buf1, const void* const* coef_arrays, int32_t n_coef,
               int64_t T, void* hip_stream, int32_t* result_index);
+
+/* girih_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * sweep, arguments, result and errors as girih_run, but the memory it needs
+ * beside the caller's buffers -- for MWD plans the pair of grid-sized arrays
+ * and the halo flag -- lives in a fixed device array of the library instead
+ * of plan-owned allocations.  It calls no hipMalloc, hipFree or other
+ * allocating routine, and records no launch timing.
+ *  Limit: each array of the grid (pitches and halos included) at most
+ *  64 MiB (e.g. 200^3 FP64, 250^3 FP32); larger MWD grids return
+ *  GIRIH_E_SCRATCH before anything is launched.  NAIVE plans need no
+ *  scratch and have no limit.
+ *  The fixed array exists once per device for the life of the process and
+ *  is shared by every call on that device: calls that overlap on one device
+ *  (other streams, other threads) race and must be serialised by the caller.
+ *  Nothing in it needs to start at zero (each run initialises what it
+ *  reads). */
+int girih_run_noalloc(girih_plan_t plan, void* buf0, void* buf1, const void* const* coef_arrays, int32_t n_coef,
+                      int64_t T, void* hip_stream, int32_t* result_index);
 
 /* Auto-tuner (paper, Section "Auto-tuning").  Allocates and initialises its
  * own arrays of the plan's grid (freed before return), times candidates with

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <vector>
@@ -82,10 +83,10 @@ struct girih_plan_s {
     const KernelEntry* kern = nullptr;   // MWD variant or naive kernel
     int R = 1;
     int64_t x_own = 0, n_xchunks = 0;
-    void* scratch[2] = {nullptr, nullptr};
+    void* work[2] = {nullptr, nullptr};  // the MWD pair beside the caller's (allocated on the first run)
     int* halo_flag = nullptr;            // device int: input halo is all zero
-    size_t scratch_bytes = 0;
-    int scratch_device = -1;
+    size_t work_bytes = 0;
+    int work_device = -1;
     Tuning tuning;
     // per-launch timing of the sweep kernels (girih_set_timing)
     bool timing = false;
@@ -315,7 +316,8 @@ int timed_launch(girih_plan_s* p, const KernelEntry* k, const void* args, dim3 g
 }
 
 template <typename Real>
-int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s) {
+int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s,
+              bool timed) {
     NaiveArgs<Real> a;
     a.g = desc_of(p);
     fill_coefs<Real>(p, coefs, a.coef);
@@ -331,27 +333,28 @@ int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs,
     for (int64_t t = 0; t < T; ++t) {
         a.V = b[t & 1];
         a.U = b[(t + 1) & 1];
-        const int rc = timed_launch(p, p->kern, &a, grid, block, s);
+        const int rc = timed ? timed_launch(p, p->kern, &a, grid, block, s)
+                             : (p->kern->launch(&a, grid, block, s) == hipSuccess ? GIRIH_OK : GIRIH_E_HIP);
         if (rc) return rc;
     }
     return GIRIH_OK;
 }
 
-int ensure_scratch(girih_plan_s* p) {
+int ensure_work(girih_plan_s* p) {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     const size_t need = grid_bytes(p);
-    if (p->scratch[0] && p->scratch_bytes == need && p->scratch_device == dev) return GIRIH_OK;
+    if (p->work[0] && p->work_bytes == need && p->work_device == dev) return GIRIH_OK;
     for (int i = 0; i < 2; ++i) {
-        if (p->scratch[i]) (void)hipFree(p->scratch[i]);
-        p->scratch[i] = nullptr;
+        if (p->work[i]) (void)hipFree(p->work[i]);
+        p->work[i] = nullptr;
     }
     for (int i = 0; i < 2; ++i) {
-        if (hipMalloc(&p->scratch[i], need) != hipSuccess) {
+        if (hipMalloc(&p->work[i], need) != hipSuccess) {
             (void)hipGetLastError();
             for (int j = 0; j < 2; ++j) {
-                if (p->scratch[j]) (void)hipFree(p->scratch[j]);
-                p->scratch[j] = nullptr;
+                if (p->work[j]) (void)hipFree(p->work[j]);
+                p->work[j] = nullptr;
             }
             return GIRIH_E_NOMEM;
         }
@@ -362,30 +365,37 @@ int ensure_scratch(girih_plan_s* p) {
         (void)hipGetLastError();
         return GIRIH_E_NOMEM;
     }
-    p->scratch_bytes = need;
-    p->scratch_device = dev;
+    p->work_bytes = need;
+    p->work_device = dev;
     return GIRIH_OK;
 }
 
+// Device memory a run uses beside the caller's buffers: the MWD pair (two
+// arrays of the grid's size) and the one-int halo flag.
+struct RunWork {
+    void* arr[2];
+    int* flag;
+};
+
 template <typename Real>
-int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s) {
-    int rc = ensure_scratch(p);
-    if (rc) return rc;
+int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, int64_t T, hipStream_t s,
+            const RunWork& w, bool timed) {
+    int rc = GIRIH_OK;
     const int64_t nx = p->grid.nx, ny = p->grid.ny, nz = p->grid.nz, h = p->grid.halo;
     const int64_t px = p->grid.pitch_x, py = p->grid.pitch_y;
     const int eb = (int)sizeof(Real);
     // every array carries buf0's fixed halo
-    HIPCHK(launch_copy_halo(buf0, p->scratch[0], eb, nx, ny, nz, h, px, py, s));
-    HIPCHK(launch_copy_halo(buf0, p->scratch[1], eb, nx, ny, nz, h, px, py, s));
-    HIPCHK(launch_zero_halo_flag(buf0, p->halo_flag, eb, nx, ny, nz, h, px, py, s));
+    HIPCHK(launch_copy_halo(buf0, w.arr[0], eb, nx, ny, nz, h, px, py, s));
+    HIPCHK(launch_copy_halo(buf0, w.arr[1], eb, nx, ny, nz, h, px, py, s));
+    HIPCHK(launch_zero_halo_flag(buf0, w.flag, eb, nx, ny, nz, h, px, py, s));
     const int dw = p->kern->dw;
     const int64_t H = dw / (2 * p->R);
     const int64_t n_rows = (T - 1) / H + 2;
     Real* user[2] = {static_cast<Real*>(buf0), static_cast<Real*>(buf1)};
-    Real* scr[2] = {static_cast<Real*>(p->scratch[0]), static_cast<Real*>(p->scratch[1])};
+    Real* scr[2] = {static_cast<Real*>(w.arr[0]), static_cast<Real*>(w.arr[1])};
     // The last row must write the caller's pair: rows alternate in -> out, so
     // row 0 reads the caller's pair iff the row count is even; otherwise u^0
-    // is first copied into the scratch pair.
+    // is first copied into the other pair.
     bool in_user = (n_rows % 2) == 0;
     if (!in_user) HIPCHK(hipMemcpyAsync(scr[0], user[0], grid_bytes(p), hipMemcpyDeviceToDevice, s));
     MwdArgs<Real> a;
@@ -393,7 +403,7 @@ int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, i
     fill_coefs<Real>(p, coefs, a.coef);
     a.T = T;
     a.x_own = (int32_t)p->x_own;
-    a.zero_halo = p->halo_flag;
+    a.zero_halo = w.flag;
     const dim3 block(p->kern->nthreads);
     for (int64_t r = 0; r < n_rows; ++r) {
         Real** in = in_user ? user : scr;
@@ -408,7 +418,8 @@ int run_mwd(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs, i
         const int64_t n_diamonds = (ny + dw / 2 - off + dw - 1) / dw;
         const dim3 grid((unsigned)p->n_xchunks, (unsigned)n_diamonds);
         const KernelEntry* k = mwd_kernel_for(p->kern, mwd_slots_needed(p->R, dw, a.t_c, T));
-        rc = timed_launch(p, k, &a, grid, block, s);
+        rc = timed ? timed_launch(p, k, &a, grid, block, s)
+                   : (k->launch(&a, grid, block, s) == hipSuccess ? GIRIH_OK : GIRIH_E_HIP);
         if (rc) return rc;
         in_user = !in_user;
     }
@@ -492,7 +503,8 @@ int alloc_tune_bufs(girih_plan_s* p, TuneBufs& b, hipStream_t s) {
     return GIRIH_OK;
 }
 
-int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s);
+int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s,
+            const RunWork* fixed = nullptr);
 
 // Adaptive test length (paper, Section "Auto-tuning": test runs are
 // lengthened until the measurement is stable).  time_reps(k) returns the
@@ -545,7 +557,7 @@ int measure(girih_plan_s* p, TuneBufs& b, hipStream_t s, int64_t T, double max_s
         return GIRIH_E_HIP;
     }
     const void* const* coefs = b.coef.empty() ? nullptr : (const void* const*)b.coef.data();
-    // warm-up (also allocates the scratch pair)
+    // warm-up (also allocates the plan's pair)
     int rc = run_any(p, b.f[0], b.f[1], coefs, T, s);
     if (rc == GIRIH_OK && hipStreamSynchronize(s) != hipSuccess) rc = GIRIH_E_HIP;
     Adapted ad;
@@ -744,14 +756,64 @@ std::vector<girih_params> naive_candidates(const girih_plan_s*) {
 }  // namespace
 
 namespace {
-int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s) {
+int run_any(girih_plan_s* p, void* b0, void* b1, const void* const* coefs, int64_t T, hipStream_t s,
+            const RunWork* fixed) {
     if (T == 0) return GIRIH_OK;
+    RunWork w{{nullptr, nullptr}, nullptr};
+    if (p->algo == GIRIH_MWD) {
+        if (fixed) {
+            w = *fixed;
+        } else {
+            const int rc = ensure_work(p);
+            if (rc) return rc;
+            w = RunWork{{p->work[0], p->work[1]}, p->halo_flag};
+        }
+    }
+    const bool timed = fixed == nullptr;
     HIPCHK(launch_copy_halo(b0, b1, (int)elem_bytes(p->dtype), p->grid.nx, p->grid.ny, p->grid.nz, p->grid.halo,
                             p->grid.pitch_x, p->grid.pitch_y, s));
     if (p->algo == GIRIH_NAIVE)
-        return p->dtype == GIRIH_F64 ? run_naive<double>(p, b0, b1, coefs, T, s)
-                                     : run_naive<float>(p, b0, b1, coefs, T, s);
-    return p->dtype == GIRIH_F64 ? run_mwd<double>(p, b0, b1, coefs, T, s) : run_mwd<float>(p, b0, b1, coefs, T, s);
+        return p->dtype == GIRIH_F64 ? run_naive<double>(p, b0, b1, coefs, T, s, timed)
+                                     : run_naive<float>(p, b0, b1, coefs, T, s, timed);
+    return p->dtype == GIRIH_F64 ? run_mwd<double>(p, b0, b1, coefs, T, s, w, timed)
+                                 : run_mwd<float>(p, b0, b1, coefs, T, s, w, timed);
+}
+}  // namespace
+
+// ------------------------------------------------ fixed scratch (no allocation)
+
+// Device memory of girih_run_noalloc, for callers that cannot allocate: the
+// halo flag (first 256 bytes), then the MWD pair of at most kFixedArrayBytes
+// each.  Every device the library runs on holds one copy for the life of the
+// process; all calls on one device share it.
+constexpr size_t kFixedFlagBytes = 256;
+constexpr size_t kFixedArrayBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedFlagBytes + 2 * kFixedArrayBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the array's name is only a host-side handle).
+int fixed_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return GIRIH_E_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return GIRIH_E_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GIRIH_OK;
 }
 }  // namespace
 
@@ -791,7 +853,7 @@ int girih_plan(girih_plan_t* out, girih_stencil stencil, girih_dtype dtype, cons
 int girih_plan_set_params(girih_plan_t p, const girih_params* params) {
     if (!p) return GIRIH_E_INVALID;
     girih_plan_s tmp = *p;
-    tmp.scratch[0] = tmp.scratch[1] = nullptr;   // not owned by the copy
+    tmp.work[0] = tmp.work[1] = nullptr;   // not owned by the copy
     tmp.halo_flag = nullptr;
     int rc = resolve(&tmp, params);
     if (rc) return rc;
@@ -812,6 +874,30 @@ int girih_run(girih_plan_t p, void* buf0, void* buf1, const void* const* coef_ar
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     p->n_timed = 0;   // the timing record covers the last run
     int rc = run_any(p, buf0, buf1, coef_arrays, T, s);
+    if (rc) return rc;
+    if (result_index) *result_index = (int32_t)(T & 1);
+    return GIRIH_OK;
+}
+
+int girih_run_noalloc(girih_plan_t p, void* buf0, void* buf1, const void* const* coef_arrays, int32_t n_coef,
+                      int64_t T, void* hip_stream, int32_t* result_index) {
+    if (!p || !buf0 || !buf1 || buf0 == buf1 || T < 0) return GIRIH_E_INVALID;
+    if (n_coef != kNCoef[p->stencil]) return GIRIH_E_INVALID;
+    if (n_coef && !coef_arrays) return GIRIH_E_INVALID;
+    for (int m = 0; m < n_coef; ++m)
+        if (!coef_arrays[m]) return GIRIH_E_INVALID;
+    if (p->algo == GIRIH_MWD && grid_bytes(p) > kFixedArrayBytes) return GIRIH_E_SCRATCH;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RunWork w{{nullptr, nullptr}, nullptr};
+    if (p->algo == GIRIH_MWD && T > 0) {
+        void* base = nullptr;
+        const int rc = fixed_scratch(&base);
+        if (rc) return rc;
+        unsigned char* b = static_cast<unsigned char*>(base);
+        w = RunWork{{b + kFixedFlagBytes, b + kFixedFlagBytes + kFixedArrayBytes}, reinterpret_cast<int*>(b)};
+    }
+    p->n_timed = 0;
+    const int rc = run_any(p, buf0, buf1, coef_arrays, T, s, &w);
     if (rc) return rc;
     if (result_index) *result_index = (int32_t)(T & 1);
     return GIRIH_OK;
@@ -962,7 +1048,7 @@ void girih_destroy(girih_plan_t p) {
     if (!p) return;
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
-        if (p->scratch[i]) (void)hipFree(p->scratch[i]);
+        if (p->work[i]) (void)hipFree(p->work[i]);
     if (p->halo_flag) (void)hipFree(p->halo_flag);
     delete p;
 }
@@ -976,6 +1062,7 @@ const char* girih_strerror(int code) {
         case GIRIH_E_HIP: return "HIP runtime error";
         case GIRIH_E_NOMEM: return "allocation failed";
         case GIRIH_E_NOGPU: return "no usable GPU";
+        case GIRIH_E_SCRATCH: return "grid exceeds the fixed scratch of girih_run_noalloc (64 MiB per array)";
         default: return "unknown error";
     }
 }

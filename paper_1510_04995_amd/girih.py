@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgirih.so")
 
 OK = 0
-E_INVALID, E_UNSUPPORTED, E_LDS, E_HIP, E_NOMEM, E_NOGPU = -1, -2, -3, -4, -5, -6
+E_INVALID, E_UNSUPPORTED, E_LDS, E_HIP, E_NOMEM, E_NOGPU, E_SCRATCH = -1, -2, -3, -4, -5, -6, -7
 
 STENCIL_IDS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3, "25l": 4}
 DTYPE_IDS = {"f64": 0, "f32": 1}
@@ -68,6 +68,9 @@ SIGNATURES = {
     "girih_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "girih_run_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "girih_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                   ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.POINTER(ctypes.c_double)]),
     "girih_tune_set_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams), ctypes.c_int32]),
@@ -163,6 +166,18 @@ def girih_run(plan, buf0_ptr, buf1_ptr, coef_ptrs, T, stream_ptr):
                           ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)) if n else None, n, int(T),
                           ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None, ctypes.byref(res))
     _check(rc, "girih_run")
+    return res.value
+
+
+def girih_run_noalloc(plan, buf0_ptr, buf1_ptr, coef_ptrs, T, stream_ptr):
+    """girih_run with the library's fixed device scratch (no allocation)."""
+    n = len(coef_ptrs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[ctypes.c_void_p(int(q)) for q in coef_ptrs]) if n else None
+    res = ctypes.c_int32(-1)
+    rc = _lib().girih_run_noalloc(plan, ctypes.c_void_p(int(buf0_ptr)), ctypes.c_void_p(int(buf1_ptr)),
+                                  ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)) if n else None, n, int(T),
+                                  ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None, ctypes.byref(res))
+    _check(rc, "girih_run_noalloc")
     return res.value
 
 
