@@ -46,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 WORKLOAD = "7pt-const-512"
+STENCIL_NAMES = {"7c": "7-point constant (c0=0.4, c1=0.1)", "25c": "25-point constant (c0..c4 drawn, normalised)"}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "mwd_7pt_const_512_f64_traffic.txt")
 KERNEL_SOURCES = ("paper_1510_04995_amd/csrc/mwd.hpp", "paper_1510_04995_amd/csrc/stencils.hpp",
                   "paper_1510_04995_amd/csrc/kernels_7c_f64.hip", "paper_1510_04995_amd/csrc/instantiate.hpp")
@@ -234,6 +235,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the naive / FP32 comparison runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-suite", action="store_true", help="skip the other workloads (per_stencil)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="workload of the timed runs (default: the headline 7-point constant 512^3; another "
+                         "constant-coefficient workload serves profiling runs of its blocked kernel)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -251,7 +255,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    w = WORKLOADS[WORKLOAD]
+    w = WORKLOADS[args.workload]
+    if w.stencil not in ("7c", "25c"):
+        print("--workload takes a constant-coefficient workload", file=sys.stderr)
+        sys.exit(2)
     h = w.radius
     u0, c, _ = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
     g0 = torch.from_numpy(u0).to(dev)
@@ -391,8 +398,8 @@ def main():
                 "%d steps (the %d-step run %.1f times over)" % (t_s, w.T, t_s / w.T))
         cpu = {"value": round(w.nx * w.ny * w.nz * t_s / dt / 1e9, 4), "unit": "GLUP/s", "cores": O.num_threads(),
                "kind": "oracle",
-               "sample": "%dx%dx%d 7-point constant FP64, %s, plain C sweep (OpenMP over z), %.1f s"
-                         % (w.nx, w.ny, w.nz, what, dt)}
+               "sample": "%dx%dx%d %s FP64, %s, plain C sweep (OpenMP over z), %.1f s"
+                         % (w.nx, w.ny, w.nz, STENCIL_NAMES[w.stencil], what, dt)}
         # the same sweep on one thread, about five seconds of it
         n_all = O.num_threads()
         O.set_num_threads(1)
@@ -424,7 +431,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "stencil": "7-point constant (c0=0.4, c1=0.1)", "stencil_id": w.stencil,
+        "config": {"workload": w.name, "stencil": STENCIL_NAMES[w.stencil], "stencil_id": w.stencil,
                    "grid": [w.nx, w.ny, w.nz], "halo": h, "T": w.T, "algo": "mwd", "params": q,
                    "lds_bytes": info["lds_bytes"], "median_run_ms": round(sorted(times)[len(times) // 2] * 1e3, 3),
                    "kernel_source_hash": src_hash},

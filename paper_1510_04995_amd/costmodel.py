@@ -166,3 +166,21 @@ def tune_with_model(sweep, model, T, k=5, max_seconds=60.0):
     n_before = len(sweep.tune_log())
     best, rate = sweep.tune("model", T, max_seconds)
     return best, rate, len(sweep.tune_log()) - n_before
+
+
+def retime(sweep, T, picks, rounds=3, max_seconds=60.0):
+    """Time the given parameter sets together, interleaved over `rounds`
+    rounds with the tuner's own measurement: {index: median GLUP/s}.  Used to
+    compare the picks of different searches under the same conditions (a
+    search's own best figure carries the noise of the moment it was taken)."""
+    cands = [picks[i] for _ in range(rounds) for i in range(len(picks))]
+    sweep.set_candidates(cands)
+    n0 = len(sweep.tune_log())
+    sweep.tune("model", T, max_seconds)
+    log = sweep.tune_log()[n0:]
+    out = {}
+    for i, p in enumerate(picks):
+        vals = sorted(r["glups"] for j, r in enumerate(log) if j % len(picks) == i and r["status"] == 0)
+        out[i] = vals[len(vals) // 2] if vals else 0.0
+    return out
+

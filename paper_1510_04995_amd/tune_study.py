@@ -55,7 +55,7 @@ def timed_tune(sw, mode, T, budget, cands=None):
     t0 = time.perf_counter()
     best, rate = sw.tune(mode, T, budget)
     return {"glups": rate, "measured": len(sw.tune_log()) - n0, "seconds": time.perf_counter() - t0,
-            "params": {k: best[k] for k in ("diamond_width", "tile_x", "threads_x", "cells_per_lane")}}
+            "params": {k: best[k] for k in ("diamond_width", "wavefront_depth", "tile_x", "threads_x", "cells_per_lane")}}
 
 
 def main():
@@ -99,8 +99,14 @@ def main():
         res["hillclimb"] = timed_tune(sw, "hillclimb", EVAL_T, args.budget)
         res["model_top5"] = timed_tune(sw, "model", EVAL_T, args.budget, model.propose(sw, EVAL_T, 5))
         res["largest_tile"] = timed_tune(sw, "model", EVAL_T, args.budget, [largest_tile_pick(sw, EVAL_T)])
-        res["model_vs_exhaustive"] = res["model_top5"]["glups"] / res["exhaustive"]["glups"]
-        res["model_vs_hillclimb"] = res["model_top5"]["glups"] / res["hillclimb"]["glups"]
+        # the four picks timed again together, interleaved, so that they are
+        # compared under the same conditions
+        methods = ("exhaustive", "hillclimb", "model_top5", "largest_tile")
+        again = C.retime(sw, EVAL_T, [res[m]["params"] for m in methods])
+        for i, m in enumerate(methods):
+            res[m]["retimed"] = again[i]
+        res["model_vs_exhaustive"] = res["model_top5"]["retimed"] / res["exhaustive"]["retimed"]
+        res["model_vs_hillclimb"] = res["model_top5"]["retimed"] / res["hillclimb"]["retimed"]
         say("eval %s %s %s: exhaustive %.1f (%d, %.1f s), hill-climb %.1f (%d), model top-5 %.1f (%d, %.1f s), "
             "largest tile %.1f -> model/exhaustive %.3f"
             % (st, dt, EVAL_GRID, res["exhaustive"]["glups"], res["exhaustive"]["measured"],
@@ -126,16 +132,25 @@ def summary(report_path, out_path, command):
              % (", ".join("%s %s T = %d" % (st, "x".join(str(v) for v in n), T) for st, n, T in TRAIN),
                 rep["train_records"], rep["train_loss_first"], rep["train_loss_last"],
                 rep["train_median_abs_log_error"], rep["train_seconds"]), "",
-             "Evaluation on an unseen grid: best measured GLUP/s (candidates measured, tuning seconds).", "",
+             "Evaluation on unseen problems: the GLUP/s of each search's pick, timed again after the "
+             "searches with the four picks interleaved (three rounds, median), then the search's own best "
+             "figure, the candidates it measured and its tuning seconds; pick = (diamond width, wavefront "
+             "depth, x tile, waves along x, cells per lane).", "",
              "| problem | grid, T | exhaustive | hill climbing | model top-5 | largest tile that fits "
              "| model / exhaustive | model / hill climbing |", "|---|---|---|---|---|---|---|---|"]
+    def pick(e):
+        p = e.get("params", {})
+        return "(%s)" % ", ".join(str(p.get(k, "")) for k in ("diamond_width", "wavefront_depth", "tile_x")
+                                  if k in p) + ("" if "threads_x" not in p else
+                                                " %dx%d" % (p["threads_x"] // 64, p["cells_per_lane"]))
     for r in rep["eval"]:
         def cell(k):
             e = r[k]
-            return "%.1f (%d, %.1f s)" % (e["glups"], e["measured"], e["seconds"])
-        lines.append("| %s %s | %s, %d | %s | %s | %s | %.1f | %.3f | %.3f |" % (
+            head = "%.1f" % e["retimed"] if "retimed" in e else "-"
+            return "%s; %.1f (%d, %.1f s) %s" % (head, e["glups"], e["measured"], e["seconds"], pick(e))
+        lines.append("| %s %s | %s, %d | %s | %s | %s | %s | %.3f | %.3f |" % (
             r["stencil"], r["dtype"], "x".join(str(v) for v in r["grid"]), r["T"], cell("exhaustive"),
-            cell("hillclimb"), cell("model_top5"), r["largest_tile"]["glups"], r["model_vs_exhaustive"],
+            cell("hillclimb"), cell("model_top5"), cell("largest_tile"), r["model_vs_exhaustive"],
             r.get("model_vs_hillclimb", r["model_top5"]["glups"] / r["hillclimb"]["glups"])))
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
