@@ -7,9 +7,9 @@
 
 namespace girih {
 
-template <class S, typename Real, int DW, int VX, int WX, int NSV>
+template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
 hipError_t launch_mwd(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
-    hipLaunchKernelGGL((mwd_row_kernel<S, Real, DW, VX, WX, NSV>), grid, block, 0, stream,
+    hipLaunchKernelGGL((mwd_row_kernel<S, Real, DW, VX, WX, NSV, NF>), grid, block, 0, stream,
                        *static_cast<const MwdArgs<Real>*>(args));
     return hipGetLastError();
 }
@@ -32,30 +32,30 @@ hipError_t launch_naive_tile(const void* args, dim3 grid, dim3 block, hipStream_
 // kernel with H + 3 slots per wave: enough for the first diamond row (levels
 // below H lie before t = 0) and for the last one (levels from H on lie at or
 // after T).
-template <class S, typename Real, int DW, int VX, int WX>
+template <class S, typename Real, int DW, int VX, int WX, int NF = 1>
 void add_mwd(std::vector<KernelEntry>& t, int st, int dt) {
-    using K = MwdKernel<S, Real, DW, VX, WX>;
+    using K = MwdKernel<S, Real, DW, VX, WX, NF>;
     constexpr int H = K::H, L = K::L;
-    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0, 0,
-                            reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0>),
-                            &launch_mwd<S, Real, DW, VX, WX, 0>});
+    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0, 0, NF,
+                            reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0, NF>),
+                            &launch_mwd<S, Real, DW, VX, WX, 0, NF>});
     if constexpr (H + 3 < L + 2)
-        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3, 0,
-                                reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3>),
-                                &launch_mwd<S, Real, DW, VX, WX, H + 3>});
+        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3, 0, NF,
+                                reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3, NF>),
+                                &launch_mwd<S, Real, DW, VX, WX, H + 3, NF>});
 }
 
 template <class S, typename Real, int BY>
 void add_naive_tile(std::vector<KernelEntry>& t, int st, int dt) {
     constexpr int R = S::R;
     t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 64 * BY, (BY + 2 * R) * (64 + 2 * R) * (int)sizeof(Real), 0,
-                            0, 1, reinterpret_cast<const void*>(&naive_tile_kernel<S, Real, BY>),
+                            0, 1, 0, reinterpret_cast<const void*>(&naive_tile_kernel<S, Real, BY>),
                             &launch_naive_tile<S, Real, BY>});
 }
 
 template <class S, typename Real>
 void add_naive(std::vector<KernelEntry>& t, int st, int dt) {
-    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0,
+    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0, 0,
                             reinterpret_cast<const void*>(&naive_step_kernel<S, Real>),
                             &launch_naive<S, Real>});
     add_naive_tile<S, Real, 4>(t, st, dt);
@@ -80,6 +80,7 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         // stencil (Dw = 12 spills in FP64).
         add_mwd<S, Real, 8, 1, 2>(t, st, dt);
         add_mwd<S, Real, 8, 2, 1>(t, st, dt);
+        add_mwd<S, Real, 8, 1, 2, 2>(t, st, dt);
         if constexpr (F64) {
             add_mwd<S, Real, 8, 1, 3>(t, st, dt);
         } else {
@@ -105,10 +106,15 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         add_mwd<S, Real, 8, 2, 2>(t, st, dt);
         add_mwd<S, Real, 12, 1, 2>(t, st, dt);
         add_mwd<S, Real, 16, 1, 1>(t, st, dt);
+        // wavefront depth 2 (two planes per step): twice the stage rows and
+        // ring registers of depth 1
+        add_mwd<S, Real, 8, 1, 2, 2>(t, st, dt);
         if constexpr (!F64) {
             add_mwd<S, Real, 8, 1, 4>(t, st, dt);
             add_mwd<S, Real, 12, 2, 1>(t, st, dt);
             add_mwd<S, Real, 16, 2, 1>(t, st, dt);
+            add_mwd<S, Real, 12, 1, 2, 2>(t, st, dt);
+            add_mwd<S, Real, 16, 1, 1, 2>(t, st, dt);
         }
     } else {
         add_mwd<S, Real, 8, 1, 2>(t, st, dt);
@@ -119,6 +125,7 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
             add_mwd<S, Real, 8, 2, 2>(t, st, dt);
             add_mwd<S, Real, 16, 2, 1>(t, st, dt);
             add_mwd<S, Real, 24, 1, 1>(t, st, dt);
+            add_mwd<S, Real, 16, 1, 1, 2>(t, st, dt);
         }
     }
 }

@@ -7,8 +7,12 @@
 //
 //  * one workgroup = one extruded diamond (tiled in (t,y)) x one x-chunk;
 //    the diamond's intermediate time levels never leave the CU;
-//  * the wavefront runs along z: at wavefront step zs, level k of the diamond
-//    updates plane zs - R*k (slope R, one plane per step: N_F = 1);
+//  * the wavefront runs along z in steps of NF planes (the wavefront depth
+//    N_F): a step advances one slab of NF consecutive planes, and at step zs
+//    level k of the diamond updates slab zs - RZ*k, RZ = ceil(R/NF) slabs
+//    (the paper skews the levels by R planes; a level here also takes its
+//    x/y neighbours of the slab from the level below's previous steps, so the
+//    skew is at least one slab);
 //  * lanes run along x (VX blocks of 64 consecutive cells), so every global
 //    access is a coalesced x-row;
 //  * threads split the diamond along y with a fixed data subset per thread
@@ -16,13 +20,14 @@
 //    each wave owns two y-rows of the diamond, row A at half-distance d from
 //    the centre and row B at H-1-d (in blocks of R rows), so every wave
 //    updates exactly L = 2H (row, level) cells per step;
-//  * each (row, level) cell keeps its last 2R outputs along z in registers
+//  * each (row, level) cell keeps its last 2*RZ slabs along z in registers
 //    (the z-ring): z-neighbours never touch memory;
-//  * the plane each level reads its x- and y-neighbours from is staged in
-//    LDS once per wavefront step: computed levels from their z-rings, and the
-//    cells of the previous diamond row a level needs (its entry inputs and
-//    the rows just outside it) from HBM, loaded one step ahead into
-//    registers so no HBM latency sits between two barriers;
+//  * the slab each level reads its x- and y-neighbours from is staged in
+//    LDS once per wavefront step (NF sub-rows per stage row): computed
+//    levels from their z-rings, and the cells of the previous diamond row a
+//    level needs (its entry inputs and the rows just outside it) from HBM,
+//    loaded one step ahead into registers so no HBM latency sits between
+//    two barriers;
 //  * a row's first computed level takes its z-neighbours from a "virtual"
 //    z-ring of the input time level, fed by the same one-step-ahead loads;
 //  * the x-chunk carries a shrinking halo of R*(L-1) cells per side that is
@@ -162,7 +167,7 @@ __host__ __device__ inline void row_levels(int j, int64_t y, int64_t ny, int64_t
     kf = (int)lo; kl = (int)hi;
 }
 
-template <class S, typename Real, int DW, int VX, int WX>
+template <class S, typename Real, int DW, int VX, int WX, int NF = 1>
 struct MwdKernel {
     static constexpr int R = S::R;
     using Sh = DiamondShape<R, DW>;
@@ -172,20 +177,27 @@ struct MwdKernel {
     static constexpr int NT = 64 * NWAVES;
     static_assert(NT <= 1024, "a workgroup holds at most 1024 threads");
     static constexpr int XL = 64 * VX * WX;     // x cells held per row
-    static constexpr int XLP = XL + 2 * R;      // LDS row stride (R guard cells per side)
+    static constexpr int XLP = XL + 2 * R;      // LDS sub-row stride (R guard cells per side)
     static constexpr int HX = R * (L - 1);      // redundant x halo per side
     static constexpr int XOWN_MAX = XL - 2 * HX;
+    // Wavefront depth: a step advances NF planes (one "slab" of NF
+    // consecutive planes per level); the z radius in slabs, and the skew of
+    // the levels in slabs, is RZ = ceil(R / NF).
+    static_assert(NF >= 1 && NF <= 4, "wavefront depth");
+    static constexpr int RZ = (R + NF - 1) / NF;
+    // a stage row holds the NF planes of a slab, one sub-row each
+    static constexpr int SROW = NF * XLP;
     // one stage buffer: stage rows plus 2R+1 spare rows that absorb the stage
     // writes and reads of slots without a stage row
     static constexpr int BUF_ROWS = Sh::STAGE_ROWS + 2 * R + 1;
-    static constexpr int BUF_BYTES = BUF_ROWS * XLP * (int)sizeof(Real);
+    static constexpr int BUF_BYTES = BUF_ROWS * SROW * (int)sizeof(Real);
     // Two stage buffers (even and odd wavefront steps) when they fit in the
     // 160 KiB of LDS a workgroup may hold: a step then needs one barrier
     // (between staging and compute) instead of two.
     static constexpr bool DB = 2 * BUF_BYTES <= 163840;
     static constexpr int LDS_ROWS = BUF_ROWS * (DB ? 2 : 1);
-    static constexpr int LDS_BYTES = LDS_ROWS * XLP * (int)sizeof(Real);
-    static constexpr int RING = 2 * R;
+    static constexpr int LDS_BYTES = LDS_ROWS * SROW * (int)sizeof(Real);
+    static constexpr int RING = 2 * RZ;         // slabs a slot keeps along z
 };
 
 // Stage duties of one owned row.  Level k of the stage holds the time level
@@ -298,12 +310,13 @@ enum : int {
 // of the run clips hold fewer slots per wave, and a kernel with fewer slots
 // does proportionally less work per step.  The host launches such a kernel
 // only for rows whose every wave fits (mwd_slots_needed).
-template <class S, typename Real, int DW, int VX, int WX, int NSV>
+template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
 __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk, const int diamond,
                                          Real* __restrict__ stage) {
-    using KK = MwdKernel<S, Real, DW, VX, WX>;
+    using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
     using Sh = typename KK::Sh;
-    constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP;
+    constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP, RZ = KK::RZ;
+    constexpr int SROW = KK::SROW;
     constexpr int NS = NSV > 0 ? NSV : L + 2;
     static_assert(NS >= 3 && NS <= L + 2, "slot count");
     // steps unrolled per loop iteration, a multiple of the two stage buffers:
@@ -311,7 +324,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
     // (at most four levels and 8 bytes per lane and ring plane), so the
     // z-rings rotate by renaming registers; otherwise two, and rings longer
     // than two planes shift by register moves
-    constexpr int UNR = (RING == 2 || (L <= 4 && VX * WX * (int)sizeof(Real) <= 8)) ? RING : 2;
+    constexpr int UNR = (RING == 2 || (L <= 4 && NF * VX * WX * (int)sizeof(Real) <= 8)) ? RING : 2;
     // HBM inputs are loaded PD steps before the step that uses them, into
     // one of PD register sets
     constexpr int PD = 1;
@@ -427,14 +440,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                       (((t_c - H + kvA + 1) & 1) ? F_PV_A : 0) | (((t_c - H + kvB + 1) & 1) ? F_PV_B : 0) |
                       ((t_c & 1) ? F_PT : 0) | (inA && !cmpA ? F_COPY_A : 0) | (inB && !cmpB ? F_COPY_B : 0);
     auto rowb_of = [&](int j) -> uint32_t { return (uint32_t)((ybase + j + hh) * pitchx * SB); };
-    auto lds_row = [&](int k, int j) -> int { return (srow0_rt<Sh>(k) + j) * XLP + R; };   // element index
+    // element index of (stage level k, local row j), sub-row 0 (sub-row f at + f*XLP)
+    auto lds_row = [&](int k, int j) -> int { return (srow0_rt<Sh>(k) + j) * SROW + R; };
     const uint32_t lane_b = (uint32_t)((cb + lane) * SB);
     // LDS byte addresses (wave-uniform part; a lane adds lane_b) of the duty
     // rows, and byte offsets (uniform part; a lane adds its x offset) of the
-    // prefetch streams from the base of their step's window (plane
-    // zs + PD - R*L): a stream at depth dz reads plane zs + PD - R*dz of its row.
+    // prefetch streams from the base of their step's window (first plane of
+    // slab zs + PD - RZ*L): a stream at depth dz reads slab zs + PD - RZ*dz of
+    // its row (plane f of the slab at + f planes).
     // Kept uniform, so they cost scalar rather than vector registers.
-    auto fo_of = [&](int dz, int j) -> uint32_t { return (uint32_t)(R * (L - dz)) * plane_b + rowb_of(j); };
+    auto fo_of = [&](int dz, int j) -> uint32_t { return (uint32_t)(NF * RZ * (L - dz)) * plane_b + rowb_of(j); };
     const uint32_t uA2 = (uint32_t)(lds_row(kvA - 1, jA) * SB), uB2 = (uint32_t)(lds_row(kvB - 1, jB) * SB),
                    uOA = (uint32_t)(lds_row(H - 1, joA) * SB), uOB = (uint32_t)(lds_row(H - 1, joB) * SB);
     const uint32_t foA = fo_of(kvA < 0 ? 0 : kvA, jA), foB = fo_of(kvB < 0 ? 0 : kvB, jB),
@@ -449,9 +464,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
     const int baseA = cmpA ? kfA - 1 : kvA, baseB = cmpB ? kfB - 1 : kvB;
     // LDS byte address (per lane) of the corner (row - R, column - R) of the
     // slot's stage row, and the slot's global byte offset within the step's
-    // window (plane of its level, its row); masks over slots.
-    constexpr int CORNER = (R * XLP + R) * SB;   // from the corner to the cell itself
-    const uint32_t spare = (uint32_t)(Sh::STAGE_ROWS * XLP * SB);
+    // window (first plane of its level's slab, its row); masks over slots.
+    constexpr int CORNER = (R * SROW + R) * SB;   // from the corner to the cell itself
+    const uint32_t spare = (uint32_t)(Sh::STAGE_ROWS * SROW * SB);
     uint32_t lcs[NS], gos[S::NCOEF > 0 ? NS : 1];
     uint32_t cmS = 0;
     static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
@@ -462,16 +477,17 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
         const int k = (isB ? baseB : baseA) + t;
         const int j = isB ? jB : jA;
         lcs[s] = in_vgpr(valid ? (uint32_t)(lds_row(k, j) * SB - CORNER) : spare) + lane_b;
-        if constexpr (S::NCOEF > 0) gos[s] = in_vgpr(valid ? (uint32_t)(R * (L - k)) * plane_b + rowb_of(j) : 0u);
+        if constexpr (S::NCOEF > 0) gos[s] = in_vgpr(valid ? (uint32_t)(NF * RZ * (L - k)) * plane_b + rowb_of(j) : 0u);
         cmS |= valid && t >= 1 ? 1u << s : 0u;
     });
     // Stores: the state a row leaves is its last two levels kl and kl-1 (for a
     // row with one level, kl-1 is its input level).  At step zs the stage row
-    // of level k holds plane zs - R*(k+1), so the stores read the two stage
+    // of level k holds slab zs - RZ*(k+1), so the stores read the two stage
     // rows back after the barrier: every plane of each level passes through
     // the stage once.  Per row the even and the odd one of the two levels
     // (time levels of opposite parity) go to out[p0^1] and out[p0].
-    // Store i: 0 = A even, 1 = A odd, 2 = B even, 3 = B odd.
+    // Store i: 0 = A even, 1 = A odd, 2 = B even, 3 = B odd (offsets of the
+    // slab's first plane; plane f of the slab at + f planes).
     uint32_t stl[4], sgo[4][VX];
     int stk[4];
 #pragma unroll
@@ -483,16 +499,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
         const int j = isB ? jB : jA;
         stk[i] = cmp ? k : -1000;
         stl[i] = in_vgpr(cmp ? (uint32_t)(lds_row(k, j) * SB) : spare) + lane_b;
-        const uint32_t u = in_vgpr(cmp ? (uint32_t)(R * (L - k - 1)) * plane_b + rowb_of(j) : 0u);
+        const uint32_t u = in_vgpr(cmp ? (uint32_t)(NF * RZ * (L - k - 1)) * plane_b + rowb_of(j) : 0u);
 #pragma unroll
         for (int v = 0; v < VX; ++v) sgo[i][v] = cmp ? ((u + xb[v]) | kill[v]) : DROP;
     }
-    // rows that compute no level copy both input levels: plane zs is R*L
-    // planes above the window base
+    // rows that compute no level copy both input levels: slab zs is RZ*L
+    // slabs above the window base
     uint32_t cpo[2][VX];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        const uint32_t u = in_vgpr((uint32_t)(R * L) * plane_b + rowb_of(t == 0 ? jA : jB));
+        const uint32_t u = in_vgpr((uint32_t)(NF * RZ * L) * plane_b + rowb_of(t == 0 ? jA : jB));
 #pragma unroll
         for (int v = 0; v < VX; ++v) cpo[t][v] = u + xb[v];
     }
@@ -510,8 +526,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                     const int y = ybase + j;
                     if ((y >= -R && y < 0) || (y >= ny && y < ny + R)) {
                         for (int b = 0; b < (KK::DB ? 2 : 1); ++b) {
-                            Real* sp = stage + b * KK::BUF_ROWS * XLP + lds_row(k, j) - R;
-                            for (int col = threadIdx.x; col < XLP; col += KK::NT) sp[col] = Real(0);
+                            Real* sp = stage + b * KK::BUF_ROWS * SROW + lds_row(k, j) - R;
+                            for (int col = threadIdx.x; col < SROW; col += KK::NT) sp[col] = Real(0);
                         }
                     }
                 }
@@ -528,12 +544,14 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
 #pragma unroll
             for (int v = 0; v < VX; ++v)
                 if (hz[v])
-                    for (int row = 0; row < KK::LDS_ROWS; ++row) stage[row * XLP + R + cb + lane + 64 * v] = Real(0);
+                    for (int row = 0; row < KK::LDS_ROWS * NF; ++row) stage[row * XLP + R + cb + lane + 64 * v] = Real(0);
         }
 
-        // wavefront steps end here: the last plane of level L-1 is computed at
-        // step nz-1 + R*(L-1) and passes through the stage R steps later
-        const int nzs = nz + R * L;
+        // wavefront steps end here: the last slab of level L-1 (slab nzq-1) is
+        // computed at step nzq-1 + RZ*(L-1) and passes through the stage RZ
+        // steps later
+        const int nzq = (nz + NF - 1) / NF;
+        const int nzs = nzq + RZ * L;
         // byte offset of plane q from the array base
         auto plane_off = [&](int q) -> int64_t { return (int64_t)(q + hh) * (int64_t)plane_b; };
         auto at = [](const Real* base, int64_t off) -> const Real* {
@@ -545,24 +563,31 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
         auto lds = [&](uint32_t byte_addr) -> Real& {
             return *reinterpret_cast<Real*>(reinterpret_cast<char*>(stage) + byte_addr);
         };
-        auto put = [&](uint32_t la, const Real (&src)[VX]) {   // la: per-lane LDS byte address
+        auto put = [&](uint32_t la, const Real (&src)[NF][VX]) {   // la: per-lane LDS byte address
 #pragma unroll
-            for (int v = 0; v < VX; ++v)
-                if (!hz[v]) lds(la + 64 * v * SB) = src[v];
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    if (!hz[v]) lds(la + (f * XLP + 64 * v) * SB) = src[f][v];
         };
-        // x-halo columns of a staged computed row when the halo is not zero
+        // x-halo columns of a staged computed row (slab q) when the halo is not zero
         auto fix_halo_cols = [&](int li, int q, int y) {   // li: element index, buffer included
-            if (q < -R || q >= nz + R) return;
-            const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
 #pragma unroll
-            for (int v = 0; v < VX; ++v)
-                if (xh[v]) stage[li + cb + lane + 64 * v] = ld_at(base, xb[v]);
+            for (int f = 0; f < NF; ++f) {
+                const int pl = NF * q + f;
+                if (pl < -R || pl >= nz + R) continue;
+                const Real* base = at(a.in[0], plane_off(pl) + (int64_t)(y + hh) * pitchx * SB);
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    if (xh[v]) stage[li + f * XLP + cb + lane + 64 * v] = ld_at(base, xb[v]);
+            }
         };
 
         // Loads of step zs + PD's inputs (see the streams above); with a
         // staging function, duty registers are first staged.
-        auto prefetch = [&](int zs, bool steady, Real (&vA)[VX], Real (&vB)[VX], Real (&dA2)[VX], Real (&dB2)[VX],
-                            Real (&rA)[VX], Real (&rB)[VX], auto&& stage_fn) __attribute__((always_inline)) {
+        auto prefetch = [&](int zs, bool steady, Real (&vA)[NF][VX], Real (&vB)[NF][VX], Real (&dA2)[NF][VX],
+                            Real (&dB2)[NF][VX], Real (&rA)[NF][VX], Real (&rB)[NF][VX],
+                            auto&& stage_fn) __attribute__((always_inline)) {
             const int f = (int)fresh_s((uint32_t)flags);
             // per-lane offsets, formed here from the uniform parts (fresh
             // copies keep the compiler from hoisting them into registers
@@ -575,17 +600,20 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                 oOA[v] = fresh_s(foOA) + xb[v];
                 oOB[v] = fresh_s(foOB) + xb[v];
             }
-            const int64_t nb = plane_off(zs + PD - R * L);
+            const int64_t nb = plane_off(NF * (zs + PD - RZ * L));
             const Real* fb0 = at(a.in[0], nb);
             const Real* fb1 = at(a.in[1], nb);
-            auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[VX]) __attribute__((always_inline)) {
-                if (!steady) {
-                    const int q = zs + PD - R * dz;
-                    if (q < -R || q >= nz + R) return;
-                }
-                const Real* base = odd ? fb1 : fb0;
+            auto fetch = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[NF][VX]) __attribute__((always_inline)) {
 #pragma unroll
-                for (int v = 0; v < VX; ++v) dst[v] = ld_at(base, o[v]);
+                for (int f = 0; f < NF; ++f) {
+                    if (!steady) {
+                        const int q = NF * (zs + PD - RZ * dz) + f;
+                        if (q < -R || q >= nz + R) continue;
+                    }
+                    const Real* base = at(odd ? fb1 : fb0, (int64_t)f * plane_b);
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) dst[f][v] = ld_at(base, o[v]);
+                }
             };
             if (f & (F_CMP_A | F_D1_A)) fetch(f & F_PV_A, kvA, oA, vA);
             if (f & (F_CMP_B | F_D1_B)) fetch(f & F_PV_B, kvB, oB, vB);
@@ -595,24 +623,27 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
             if (f & F_O_B) { stage_fn(fresh_s(uOB) + lane_b, rB); fetch(f & F_PT, H, oOB, rB); }
         };
 
-        Real ring[NS][RING][VX];
+        Real ring[NS][RING][NF][VX];
         // Prefetch registers, one set per step parity.  qA/qB: the input level
         // kv of a row (its input ring);
         // p2: duty level kv-1; po: the out-of-span row.
-        Real qA[PD][VX], qB[PD][VX], p2A[PD][VX], p2B[PD][VX], poA[PD][VX], poB[PD][VX];
-        // copied levels (row A / B, input array 0 / 1) of plane zs + PD
-        Real cpv[PD][2][2][VX];
+        Real qA[PD][NF][VX], qB[PD][NF][VX], p2A[PD][NF][VX], p2B[PD][NF][VX], poA[PD][NF][VX], poB[PD][NF][VX];
+        // copied levels (row A / B, input array 0 / 1) of slab zs + PD
+        Real cpv[PD][2][2][NF][VX];
 #pragma unroll
-        for (int v = 0; v < VX; ++v) {
+        for (int f = 0; f < NF; ++f) {
 #pragma unroll
-            for (int c = 0; c < PD; ++c) {
-                qA[c][v] = qB[c][v] = p2A[c][v] = p2B[c][v] = poA[c][v] = poB[c][v] = Real(0);
-                cpv[c][0][0][v] = cpv[c][0][1][v] = cpv[c][1][0][v] = cpv[c][1][1][v] = Real(0);
-            }
+            for (int v = 0; v < VX; ++v) {
 #pragma unroll
-            for (int m = 0; m < RING; ++m) {
+                for (int c = 0; c < PD; ++c) {
+                    qA[c][f][v] = qB[c][f][v] = p2A[c][f][v] = p2B[c][f][v] = poA[c][f][v] = poB[c][f][v] = Real(0);
+                    cpv[c][0][0][f][v] = cpv[c][0][1][f][v] = cpv[c][1][0][f][v] = cpv[c][1][1][f][v] = Real(0);
+                }
 #pragma unroll
-                for (int i = 0; i < NS; ++i) ring[i][m][v] = Real(0);
+                for (int m = 0; m < RING; ++m) {
+#pragma unroll
+                    for (int i = 0; i < NS; ++i) ring[i][m][f][v] = Real(0);
+                }
             }
         }
 
@@ -633,26 +664,34 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                 lcs[i] = fresh_v(lcs[i]);
                 gos[i] = fresh_v(gos[i]);
             }
-            Real vcA[VX], vcB[VX];
+            Real vcA[NF][VX], vcB[NF][VX];
 #pragma unroll
-            for (int v = 0; v < VX; ++v) { vcA[v] = qA[ph % PD][v]; vcB[v] = qB[ph % PD][v]; }
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) { vcA[f][v] = qA[ph % PD][f][v]; vcB[f][v] = qB[ph % PD][f][v]; }
             // ---- A: stage every plane the levels read this step ------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
-                // copied levels of plane zs, loaded one step ago (before this
+                // copied levels of slab zs, loaded one step ago (before this
                 // step's loads reuse the registers)
                 if constexpr (CPF) {
-                    if ((f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
-                        const int64_t e0b = plane_off(zs - R * L);
+                    if ((f & (F_COPY_A | F_COPY_B)) && zs >= 0 && NF * zs < nz) {
+                        const int64_t e0b = plane_off(NF * (zs - RZ * L));
                         const __amdgpu_buffer_rsrc_t o0 = raw_rsrc(atw(a.out[0], e0b)),
                                                      o1 = raw_rsrc(atw(a.out[1], e0b));
 #pragma unroll
                         for (int t = 0; t < 2; ++t) {
                             if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
 #pragma unroll
-                                for (int v = 0; v < VX; ++v) {
-                                    buf_store(o0, cpo[t][v] | kill[v], cpv[ph % PD][t][0][v]);
-                                    buf_store(o1, cpo[t][v] | kill[v], cpv[ph % PD][t][1][v]);
+                                for (int g = 0; g < NF; ++g) {
+                                    // planes of the slab beyond the grid are dropped
+                                    const uint32_t zd = NF * zs + g < nz ? 0u : DROP;
+#pragma unroll
+                                    for (int v = 0; v < VX; ++v) {
+                                        const uint32_t o = (cpo[t][v] + g * plane_b) | kill[v] | zd;
+                                        buf_store(o0, o, cpv[ph % PD][t][0][g][v]);
+                                        buf_store(o1, o, cpv[ph % PD][t][1][g][v]);
+                                    }
                                 }
                             }
                         }
@@ -665,31 +704,37 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                     if (!hz[v]) {
                         static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
                             constexpr int s = decltype(sc)::value;
-                            lds(lcs[s] + BOFF + CORNER + 64 * v * SB) = ring[s][P(R)][v];
+#pragma unroll
+                            for (int g = 0; g < NF; ++g)
+                                lds(lcs[s] + BOFF + CORNER + (g * XLP + 64 * v) * SB) = ring[s][P(RZ)][g][v];
                         });
                     }
                 }
                 // loads for step zs + PD into this step's register set (its
-                // values are consumed above or copied to vcA/vcB): plane
-                // zs + PD - R*dz of each stream; planes outside the haloed grid
+                // values are consumed above or copied to vcA/vcB): slab
+                // zs + PD - RZ*dz of each stream; planes outside the haloed grid
                 // are skipped (no computing cell reads them; in the steady range
                 // every plane is inside).  A duty register is staged before its
                 // next load is issued.
                 prefetch(zs, STEADY, qA[ph % PD], qB[ph % PD], p2A[ph % PD], p2B[ph % PD], poA[ph % PD], poB[ph % PD],
-                         [&](uint32_t la, const Real (&src)[VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
+                         [&](uint32_t la, const Real (&src)[NF][VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
                 if constexpr (CPF) {
-                    const int q = zs + PD;   // the plane the copy stores at step zs + PD
-                    if ((f & (F_COPY_A | F_COPY_B)) && q >= 0 && q < nz) {
-                        const int64_t nb = plane_off(q - R * L);
-                        const Real* fb0 = at(a.in[0], nb);
-                        const Real* fb1 = at(a.in[1], nb);
+                    const int q = zs + PD;   // the slab the copy stores at step zs + PD
+                    if ((f & (F_COPY_A | F_COPY_B)) && q >= 0 && NF * q < nz) {
+                        const int64_t nb = plane_off(NF * (q - RZ * L));
 #pragma unroll
-                        for (int t = 0; t < 2; ++t) {
-                            if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
+                        for (int g = 0; g < NF; ++g) {
+                            if (NF * q + g >= nz) continue;
+                            const Real* fb0 = at(a.in[0], nb + (int64_t)g * plane_b);
+                            const Real* fb1 = at(a.in[1], nb + (int64_t)g * plane_b);
 #pragma unroll
-                                for (int v = 0; v < VX; ++v) {
-                                    cpv[ph % PD][t][0][v] = ld_at(fb0, cpo[t][v]);
-                                    cpv[ph % PD][t][1][v] = ld_at(fb1, cpo[t][v]);
+                            for (int t = 0; t < 2; ++t) {
+                                if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
+#pragma unroll
+                                    for (int v = 0; v < VX; ++v) {
+                                        cpv[ph % PD][t][0][g][v] = ld_at(fb0, cpo[t][v]);
+                                        cpv[ph % PD][t][1][g][v] = ld_at(fb1, cpo[t][v]);
+                                    }
                                 }
                             }
                         }
@@ -700,18 +745,20 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                 if (!ZH && (f & (F_EDGE_X | F_EDGE_Y))) {
                     if (f & F_EDGE_X) {
                         for (int k = kfA; k <= klA && k <= L - 2; ++k)
-                            fix_halo_cols(lds_row(k, jA) + BOFE, zs - R * (k + 1), ybase + jA);
+                            fix_halo_cols(lds_row(k, jA) + BOFE, zs - RZ * (k + 1), ybase + jA);
                         for (int k = kfB; k <= klB && k <= L - 2; ++k)
-                            fix_halo_cols(lds_row(k, jB) + BOFE, zs - R * (k + 1), ybase + jB);
+                            fix_halo_cols(lds_row(k, jB) + BOFE, zs - RZ * (k + 1), ybase + jB);
                     }
                     if (f & F_EDGE_Y) {
                         for (int k = wave; k < L - 1; k += KK::NWAVES) {
                             for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
                                 const int y = ybase + j;
-                                const int q = zs - R * (k + 1);
-                                if (((y >= -R && y < 0) || (y >= ny && y < ny + R)) && q >= -R && q < nz + R) {
+                                if (!((y >= -R && y < 0) || (y >= ny && y < ny + R))) continue;
+                                for (int g = 0; g < NF; ++g) {
+                                    const int q = NF * (zs - RZ * (k + 1)) + g;
+                                    if (q < -R || q >= nz + R) continue;
                                     const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
-                                    const int li = lds_row(k, j) + BOFE;
+                                    const int li = lds_row(k, j) + BOFE + g * XLP;
                                     for (int col = lane; col < KK::XL; col += 64) {
                                         const int x = x0 + col;
                                         const int xc = x < -R ? -R : (x >= nx + R ? nx + R - 1 : x);
@@ -727,8 +774,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
             // ---- B: update every (row, level) slot of this step ----------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
-                // window of this step: planes [zs - R*L, zs]
-                const int64_t e0b = plane_off(zs - R * L);
+                // window of this step: slabs [zs - RZ*L, zs]
+                const int64_t e0b = plane_off(NF * (zs - RZ * L));
                 // the rows' last two levels, from the stage (see above).  With
                 // one stage buffer they are read back after the update, when
                 // waves that finished early would otherwise wait at the
@@ -738,54 +785,69 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                     const __amdgpu_buffer_rsrc_t rs_odd = raw_rsrc(atw(a.out[p0], e0b));
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        uint32_t zd = 0;
-                        if constexpr (!STEADY) {
-                            const int q = zs - R * (stk[i] + 1);
-                            zd = q >= 0 && q < nz ? 0u : DROP;
-                        }
 #pragma unroll
-                        for (int v = 0; v < VX; ++v)
-                            buf_store((i & 1) ? rs_odd : rs_even, sgo[i][v] | zd, lds(stl[i] + BOFF + 64 * v * SB));
+                        for (int g = 0; g < NF; ++g) {
+                            uint32_t zd = 0;
+                            if constexpr (!STEADY) {
+                                const int q = NF * (zs - RZ * (stk[i] + 1)) + g;
+                                zd = q >= 0 && q < nz ? 0u : DROP;
+                            }
+#pragma unroll
+                            for (int v = 0; v < VX; ++v)
+                                buf_store((i & 1) ? rs_odd : rs_even, (sgo[i][v] + g * plane_b) | zd,
+                                          lds(stl[i] + BOFF + (g * XLP + 64 * v) * SB));
+                        }
                     }
                 };
                 if constexpr (KK::DB) store_levels();
                 const uint32_t cm = fresh_s(cmS);
                 const int sb = (int)fresh_s((uint32_t)sB);
-                uint32_t zS = 0xffffffffu;   // slots whose level's plane zs - R*k lies inside the grid
-                if constexpr (!STEADY) {
-                    const int khz = zs >= 0 ? zs / R : -1;
-                    const int klz = zs - nz >= 0 ? (zs - nz) / R + 1 : 0;
-                    zS = (bit_range(klz - baseA, khz - baseA) & maskA) | (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA);
+                // per plane g of the slab: slots whose level's plane
+                // NF*(zs - RZ*k) + g lies inside the grid
+                uint32_t zS[NF];
+#pragma unroll
+                for (int g = 0; g < NF; ++g) {
+                    zS[g] = 0xffffffffu;
+                    if constexpr (!STEADY) {
+                        const int pz = NF * zs + g;
+                        const int khz = pz >= 0 ? pz / (NF * RZ) : -1;
+                        const int klz = pz - nz >= 0 ? (pz - nz) / (NF * RZ) + 1 : 0;
+                        zS[g] = (bit_range(klz - baseA, khz - baseA) & maskA) |
+                                (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA);
+                    }
                 }
-                Real prev[VX];
+                Real prev[NF][VX];
                 // x/y neighbours of a slot, read from the stage one slot ahead
                 // of its use (a one-deep software pipeline: deeper prefetching
                 // would hold too many registers)
-                Real nb[LDEP + 1][4 * R][VX];
+                Real nb[LDEP + 1][4 * R][NF][VX];
                 auto load_nb = [&](auto tc) __attribute__((always_inline)) {
                     constexpr int t = decltype(tc)::value;
                     const uint32_t lb = lcs[t - 1] + BOFF;     // corner of (level - 1, row)
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        const uint32_t c0 = lb + 64 * v * SB + CORNER;
-                        if constexpr (XDPP) {
-                            // the level below's plane at the neighbouring lanes is
-                            // what they staged: their ring position R
-                            nb[t % (LDEP + 1)][2][v] = lds(c0 + XLP * SB);
-                            nb[t % (LDEP + 1)][3][v] = lds(c0 - XLP * SB);
-                            const Real cc = ring[t - 1][P(R)][v];
-                            Real xp = lane_shift<0x130>(cc), xm = lane_shift<0x138>(cc);
-                            if (mxp[v]) xp = lds(c0 + SB);
-                            if (mxm[v]) xm = lds(c0 - SB);
-                            nb[t % (LDEP + 1)][0][v] = xp;
-                            nb[t % (LDEP + 1)][1][v] = xm;
-                        } else {
+                    for (int g = 0; g < NF; ++g) {
 #pragma unroll
-                            for (int r = 1; r <= R; ++r) {
-                                nb[t % (LDEP + 1)][r - 1][v] = lds(c0 + r * SB);
-                                nb[t % (LDEP + 1)][R + r - 1][v] = lds(c0 - r * SB);
-                                nb[t % (LDEP + 1)][2 * R + r - 1][v] = lds(c0 + r * XLP * SB);
-                                nb[t % (LDEP + 1)][3 * R + r - 1][v] = lds(c0 - r * XLP * SB);
+                        for (int v = 0; v < VX; ++v) {
+                            const uint32_t c0 = lb + (g * XLP + 64 * v) * SB + CORNER;
+                            if constexpr (XDPP) {
+                                // the level below's plane at the neighbouring lanes is
+                                // what they staged: their ring position RZ
+                                nb[t % (LDEP + 1)][2][g][v] = lds(c0 + SROW * SB);
+                                nb[t % (LDEP + 1)][3][g][v] = lds(c0 - SROW * SB);
+                                const Real cc = ring[t - 1][P(RZ)][g][v];
+                                Real xp = lane_shift<0x130>(cc), xm = lane_shift<0x138>(cc);
+                                if (mxp[v]) xp = lds(c0 + SB);
+                                if (mxm[v]) xm = lds(c0 - SB);
+                                nb[t % (LDEP + 1)][0][g][v] = xp;
+                                nb[t % (LDEP + 1)][1][g][v] = xm;
+                            } else {
+#pragma unroll
+                                for (int r = 1; r <= R; ++r) {
+                                    nb[t % (LDEP + 1)][r - 1][g][v] = lds(c0 + r * SB);
+                                    nb[t % (LDEP + 1)][R + r - 1][g][v] = lds(c0 - r * SB);
+                                    nb[t % (LDEP + 1)][2 * R + r - 1][g][v] = lds(c0 + r * SROW * SB);
+                                    nb[t % (LDEP + 1)][3 * R + r - 1][g][v] = lds(c0 - r * SROW * SB);
+                                }
                             }
                         }
                     }
@@ -800,126 +862,158 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
                     // its last slots alone.)
                     constexpr int PRI = 3 - (4 * s) / NS;
                     if constexpr (s == 0 || PRI != 3 - (4 * (s - 1)) / NS) __builtin_amdgcn_s_setprio(PRI);
-                    Real nv[VX];
+                    Real nv[NF][VX];
                     if constexpr (s == 0) {
 #pragma unroll
-                        for (int v = 0; v < VX; ++v) nv[v] = vcA[v];
+                        for (int g = 0; g < NF; ++g)
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) nv[g][v] = vcA[g][v];
                     } else {
                         // every slot is computed (unused slots compute values nobody reads)
-                        // a computed level whose plane lies inside the grid (unused
-                        // slots never count: their offsets are not theirs to load)
-                        const bool zv = ((cm & zS) >> s) & 1u;
                         if constexpr (s + LDEP < NS) load_nb(std::integral_constant<int, s + LDEP>{});
                         // issue those reads before this slot's arithmetic
                         __builtin_amdgcn_sched_barrier(0);
                         if constexpr (SBK >= 0 && s == SBK) {
-                            // row B's input slot takes the loaded input plane (no arithmetic)
+                            // row B's input slot takes the loaded input slab (no arithmetic)
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
+                            for (int g = 0; g < NF; ++g)
+#pragma unroll
+                                for (int v = 0; v < VX; ++v) nv[g][v] = vcB[g][v];
                         } else {
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) {
-                                Nbhd<Real, R> n;
-                                n.c = ring[s - 1][P(R)][v];
+                            for (int g = 0; g < NF; ++g) {
+                                // a computed level whose plane g lies inside the grid
+                                // (unused slots never count: their offsets are not
+                                // theirs to load)
+                                const bool zv = ((cm & zS[g]) >> s) & 1u;
 #pragma unroll
-                                for (int r = 1; r <= R; ++r) {
-                                    n.zm[r - 1] = ring[s - 1][P(R - r)][v];
-                                    n.zp[r - 1] = r == R ? prev[v] : ring[s - 1][P(R + r)][v];
-                                    n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][v];
-                                    n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][v];
-                                    n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][v];
-                                    n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][v];
-                                }
-                                Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
-                                if constexpr (S::NCOEF > 0) {
-                                    // Coefficients of the slot's plane.  In the steady range
-                                    // every slot's offset (0 for unused slots: the window's
-                                    // first plane, zs - R*L >= -R) stays inside the arrays;
-                                    // elsewhere only slots whose plane is inside the grid load.
-                                    if (STEADY || zv) {
-                                        const uint32_t go = gos[s] + xb[v];
+                                for (int v = 0; v < VX; ++v) {
+                                    Nbhd<Real, R> n;
+                                    n.c = ring[s - 1][P(RZ)][g][v];
 #pragma unroll
-                                        for (int m = 0; m < S::NCOEF; ++m) cf[m] = ld_at(at(a.coef.arr[m], e0b), go);
-                                    } else {
-#pragma unroll
-                                        for (int m = 0; m < S::NCOEF; ++m) cf[m] = Real(0);
+                                    for (int r = 1; r <= R; ++r) {
+                                        // plane g -/+ r of the slab: slab offset floor((g -/+ r) / NF),
+                                        // plane within it; ring position RZ + that offset, where
+                                        // position 2*RZ is the slab slot s-1 computed this step
+                                        const int dm = g - r, dp = g + r;
+                                        const int sm = dm >= 0 ? dm / NF : -((-dm + NF - 1) / NF);
+                                        const int sp = dp / NF;
+                                        n.zm[r - 1] = ring[s - 1][P(RZ + sm)][dm - sm * NF][v];
+                                        n.zp[r - 1] = RZ + sp == RING ? prev[dp - sp * NF][v]
+                                                                      : ring[s - 1][P(RZ + sp)][dp - sp * NF][v];
+                                        n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][g][v];
+                                        n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][g][v];
+                                        n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][g][v];
+                                        n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][g][v];
                                     }
+                                    Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
+                                    if constexpr (S::NCOEF > 0) {
+                                        // Coefficients of the slot's plane.  In the steady range
+                                        // every slot's offset (0 for unused slots: the window's
+                                        // first plane, NF*(zs - RZ*L) >= 0) stays inside the
+                                        // arrays; elsewhere only slots whose plane is inside the
+                                        // grid load.
+                                        if (STEADY || zv) {
+                                            const uint32_t go = gos[s] + xb[v];
+#pragma unroll
+                                            for (int m = 0; m < S::NCOEF; ++m)
+                                                cf[m] = ld_at(at(a.coef.arr[m], e0b + (int64_t)g * plane_b), go);
+                                        } else {
+#pragma unroll
+                                            for (int m = 0; m < S::NCOEF; ++m) cf[m] = Real(0);
+                                        }
+                                    }
+                                    nv[g][v] = S::apply(n, a.coef.k, cf);
                                 }
-                                nv[v] = S::apply(n, a.coef.k, cf);
-                            }
-                            if constexpr (!STEADY) {
-                                // a level whose plane is a halo plane (or beyond) holds the halo
-                                if (!zv) {
+                                if constexpr (!STEADY) {
+                                    // a level whose plane is a halo plane (or beyond) holds the halo
+                                    if (!zv) {
 #pragma unroll
-                                    for (int v = 0; v < VX; ++v) nv[v] = Real(0);
-                                    if constexpr (!ZH) {
-                                        // halo values, for computed levels only (an unused
-                                        // slot's row may lie outside the grid)
-                                        const bool isB = s >= sb;
-                                        const int k = isB ? baseB + (s - sb) : baseA + s;
-                                        const int q = zs - R * k;
-                                        if (((cm >> s) & 1u) && q >= -R && q < nz + R) {
-                                            const Real* base =
-                                                at(a.in[0], plane_off(q) + (int64_t)(ybase + (isB ? jB : jA) + hh) * pitchx * SB);
+                                        for (int v = 0; v < VX; ++v) nv[g][v] = Real(0);
+                                        if constexpr (!ZH) {
+                                            // halo values, for computed levels only (an unused
+                                            // slot's row may lie outside the grid)
+                                            const bool isB = s >= sb;
+                                            const int k = isB ? baseB + (s - sb) : baseA + s;
+                                            const int q = NF * (zs - RZ * k) + g;
+                                            if (((cm >> s) & 1u) && q >= -R && q < nz + R) {
+                                                const Real* base = at(
+                                                    a.in[0], plane_off(q) + (int64_t)(ybase + (isB ? jB : jA) + hh) * pitchx * SB);
 #pragma unroll
-                                            for (int v = 0; v < VX; ++v) nv[v] = ld_at(base, xb[v]);
+                                                for (int v = 0; v < VX; ++v) nv[g][v] = ld_at(base, xb[v]);
+                                            }
                                         }
                                     }
                                 }
                             }
-                            // row B's input slot takes the loaded input plane
+                            // row B's input slot takes the loaded input slab
                             if constexpr (SBK < 0) {
                                 if (s == sb) {
 #pragma unroll
-                                    for (int v = 0; v < VX; ++v) nv[v] = vcB[v];
+                                    for (int g = 0; g < NF; ++g)
+#pragma unroll
+                                        for (int v = 0; v < VX; ++v) nv[g][v] = vcB[g][v];
                                 }
                             }
                         }
-                        // slot s-1's ring takes its newest plane
+                        // slot s-1's ring takes its newest slab
 #pragma unroll
-                        for (int v = 0; v < VX; ++v) {
-                            if constexpr (UNR == RING) {
-                                ring[s - 1][P(0)][v] = prev[v];
-                            } else {
+                        for (int g = 0; g < NF; ++g) {
 #pragma unroll
-                                for (int m = 0; m + 1 < RING; ++m) ring[s - 1][m][v] = ring[s - 1][m + 1][v];
-                                ring[s - 1][RING - 1][v] = prev[v];
+                            for (int v = 0; v < VX; ++v) {
+                                if constexpr (UNR == RING) {
+                                    ring[s - 1][P(0)][g][v] = prev[g][v];
+                                } else {
+#pragma unroll
+                                    for (int m = 0; m + 1 < RING; ++m) ring[s - 1][m][g][v] = ring[s - 1][m + 1][g][v];
+                                    ring[s - 1][RING - 1][g][v] = prev[g][v];
+                                }
                             }
                         }
                     }
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        // pin the slot's result here: the arithmetic of a slot
-                        // must not sink below later slots' reads, whose results
-                        // would otherwise all be held in registers at once
-                        asm volatile("" : "+v"(nv[v]));
-                        prev[v] = nv[v];
+                    for (int g = 0; g < NF; ++g) {
+#pragma unroll
+                        for (int v = 0; v < VX; ++v) {
+                            // pin the slot's result here: the arithmetic of a slot
+                            // must not sink below later slots' reads, whose results
+                            // would otherwise all be held in registers at once
+                            asm volatile("" : "+v"(nv[g][v]));
+                            prev[g][v] = nv[g][v];
+                        }
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 });
 #pragma unroll
-                for (int v = 0; v < VX; ++v) {
-                    if constexpr (UNR == RING) {
-                        ring[NS - 1][P(0)][v] = prev[v];
-                    } else {
+                for (int g = 0; g < NF; ++g) {
 #pragma unroll
-                        for (int m = 0; m + 1 < RING; ++m) ring[NS - 1][m][v] = ring[NS - 1][m + 1][v];
-                        ring[NS - 1][RING - 1][v] = prev[v];
+                    for (int v = 0; v < VX; ++v) {
+                        if constexpr (UNR == RING) {
+                            ring[NS - 1][P(0)][g][v] = prev[g][v];
+                        } else {
+#pragma unroll
+                            for (int m = 0; m + 1 < RING; ++m) ring[NS - 1][m][g][v] = ring[NS - 1][m + 1][g][v];
+                            ring[NS - 1][RING - 1][g][v] = prev[g][v];
+                        }
                     }
                 }
                 if constexpr (!KK::DB) store_levels();
                 // rows of this diamond with no level in this row: carry both
                 // levels (the clipped instance stored them in phase A)
-                if (!CPF && (f & (F_COPY_A | F_COPY_B)) && zs >= 0 && zs < nz) {
+                if (!CPF && (f & (F_COPY_A | F_COPY_B)) && zs >= 0 && NF * zs < nz) {
                     const __amdgpu_buffer_rsrc_t o0 = raw_rsrc(atw(a.out[0], e0b)), o1 = raw_rsrc(atw(a.out[1], e0b));
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
+                    for (int g = 0; g < NF; ++g) {
+                        if (NF * zs + g >= nz) continue;
 #pragma unroll
-                            for (int v = 0; v < VX; ++v) {
-                                const uint32_t o = cpo[t][v];
-                                buf_store(o0, o | kill[v], ld_at(at(a.in[0], e0b), o));
-                                buf_store(o1, o | kill[v], ld_at(at(a.in[1], e0b), o));
+                        for (int t = 0; t < 2; ++t) {
+                            if (f & (t == 0 ? F_COPY_A : F_COPY_B)) {
+#pragma unroll
+                                for (int v = 0; v < VX; ++v) {
+                                    const uint32_t o = cpo[t][v] + g * plane_b;
+                                    buf_store(o0, o | kill[v], ld_at(at(a.in[0], e0b), o));
+                                    buf_store(o1, o | kill[v], ld_at(at(a.in[1], e0b), o));
+                                }
                             }
                         }
                     }
@@ -928,17 +1022,18 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
             if constexpr (!KK::DB) __syncthreads();   // with two buffers the next step's staging may overlap
         };
 
-        // the sweep starts 2R steps early so that the input rings of rows
+        // the sweep starts 2*RZ steps early so that the input rings of rows
         // entering at level 1 hold the halo planes -R..-1; steps [zA, zB) are
-        // steady: every level's plane zs - R*k (k = 0..L-1) and every stored
-        // plane zs - R*(k+1) is inside the grid
-        const int zA = ((R * L + UNR - 1) / UNR) * UNR;
-        // (and the loads of step zs + PD stay inside the haloed grid: for R = 1
-        // the steady range ends one plane early)
-        const int zB0 = R >= PD ? nz : nz + R - PD;
+        // steady: every plane of every level's slab zs - RZ*k (k = 0..L-1) and
+        // of every stored slab zs - RZ*(k+1) is inside the grid
+        const int zA = ((RZ * L + UNR - 1) / UNR) * UNR;
+        // (slab zs's planes end at or below nz, and the planes of slab zs + PD,
+        // loaded one step ahead, stay inside the haloed grid)
+        const int zB1 = nz / NF, zB2 = (nz + R - NF) / NF - PD + 1;
+        const int zB0 = zB1 < zB2 ? zB1 : zB2;
         const int zB = (zB0 / UNR) * UNR > zA ? (zB0 / UNR) * UNR : zA;
         // first loads: the inputs of steps -RING and -RING + 1
-        auto no_stage = [](uint32_t, const Real (&)[VX]) {};
+        auto no_stage = [](uint32_t, const Real (&)[NF][VX]) {};
         static_for<0, PD>([&](auto pc) __attribute__((always_inline)) {
             constexpr int c = decltype(pc)::value;
             prefetch(-RING - PD + c, false, qA[c], qB[c], p2A[c], p2B[c], poA[c], poB[c], no_stage);
@@ -1000,13 +1095,13 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t launch_id, uint32_t 
 }
 
 // One diamond row: one workgroup per (diamond, x-chunk) tile.
-template <class S, typename Real, int DW, int VX, int WX, int NSV>
+template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
 __global__ void __launch_bounds__(64 * (DW / 2) * WX)
 mwd_row_kernel(MwdArgs<Real> a) {
-    using KK = MwdKernel<S, Real, DW, VX, WX>;
-    __shared__ Real stage[KK::LDS_ROWS * KK::XLP];
+    using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
+    __shared__ Real stage[KK::LDS_ROWS * KK::SROW];
     const uint32_t tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    mwd_tile<S, Real, DW, VX, WX, NSV>(a, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage);
+    mwd_tile<S, Real, DW, VX, WX, NSV, NF>(a, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage);
 }
 
 }  // namespace girih

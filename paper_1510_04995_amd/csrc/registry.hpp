@@ -25,6 +25,7 @@ struct KernelEntry {
     int xown_max;    // MWD: largest owned x tile
     int ns;          // MWD: register slots per wave (0: all L + 2; fewer: rows clipped by the run's time bounds)
     int variant;     // naive: 0 = neighbours through the caches, 1 = plane tiles in LDS (nthreads = 64 x rows)
+    int nf;          // MWD: wavefront depth (planes per wavefront step)
     const void* func;
     LaunchFn launch;
 };

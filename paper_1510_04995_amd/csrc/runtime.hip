@@ -103,10 +103,10 @@ size_t grid_bytes(const girih_plan_s* p) {
            elem_bytes(p->dtype);
 }
 
-const KernelEntry* find_mwd(int st, int dt, int dw, int vx, int wx) {
+const KernelEntry* find_mwd(int st, int dt, int dw, int vx, int wx, int nf) {
     for (const auto& e : kernel_table())
         if (e.algo == AL_MWD && e.stencil == st && e.dtype == dt && e.dw == dw && e.vx == vx && e.wx == wx &&
-            e.ns == 0)
+            e.nf == nf && e.ns == 0)
             return &e;
     return nullptr;
 }
@@ -141,7 +141,8 @@ const KernelEntry* mwd_kernel_for(const KernelEntry* full, int need) {
     const KernelEntry* best = full;
     for (const auto& e : kernel_table())
         if (e.algo == AL_MWD && e.stencil == full->stencil && e.dtype == full->dtype && e.dw == full->dw &&
-            e.vx == full->vx && e.wx == full->wx && e.ns > 0 && e.ns >= need && (best->ns == 0 || e.ns < best->ns))
+            e.vx == full->vx && e.wx == full->wx && e.nf == full->nf && e.ns > 0 && e.ns >= need &&
+            (best->ns == 0 || e.ns < best->ns))
             best = &e;
     return best;
 }
@@ -213,12 +214,15 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         if (vx == 0) vx = 1;
         if (wx == 0) wx = 1;
         if (dw <= 0 || dw % (2 * R) || (R == 1 && dw % 4)) return GIRIH_E_INVALID;
-        if (q.wavefront_depth != 0 && q.wavefront_depth != 1) return GIRIH_E_UNSUPPORTED;
+        const int nf = q.wavefront_depth ? q.wavefront_depth : 1;
+        if (nf < 0) return GIRIH_E_INVALID;
         if (q.variant != 0) return GIRIH_E_UNSUPPORTED;
-        const KernelEntry* k = find_mwd(p->stencil, p->dtype, dw, vx, wx);
+        const KernelEntry* k = find_mwd(p->stencil, p->dtype, dw, vx, wx, nf);
         if (!k) return GIRIH_E_UNSUPPORTED;
-        // the kernel addresses a window of R*(L+1) planes with 32-bit offsets
-        const int64_t win = (int64_t)R * (dw / R + 1) + 1;
+        // the kernel addresses a window of nf*(RZ*(L+1)+1) planes (RZ = ceil(R/nf))
+        // with 32-bit offsets
+        const int64_t rz = (R + nf - 1) / nf;
+        const int64_t win = (int64_t)nf * (rz * (dw / R + 1) + 1);
         if (win * p->grid.pitch_y * p->grid.pitch_x * (int64_t)elem_bytes(p->dtype) >= (int64_t)1 << 31)
             return GIRIH_E_UNSUPPORTED;
         int64_t xo = q.tile_x ? q.tile_x : default_x_tile(p, k, dw);
@@ -229,7 +233,7 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         p->x_own = xo;
         p->n_xchunks = (p->grid.nx + xo - 1) / xo;
         q.diamond_width = dw;
-        q.wavefront_depth = 1;
+        q.wavefront_depth = nf;
         q.tile_x = (int32_t)xo;
         q.tile_y = dw;
         q.tile_z = (int32_t)std::min<int64_t>(p->grid.nz, INT32_MAX);
@@ -712,7 +716,7 @@ std::vector<girih_params> mwd_candidates(const girih_plan_s* p) {
         for (int64_t t : tiles) {
             girih_params q{};
             q.diamond_width = e.dw;
-            q.wavefront_depth = 1;
+            q.wavefront_depth = e.nf;
             q.tile_x = (int32_t)t;
             q.threads_x = 64 * e.wx;
             q.cells_per_lane = e.vx;

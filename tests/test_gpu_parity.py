@@ -129,8 +129,8 @@ MWD_CASES = [
 ]
 
 
-def mwd_params(dw, vx, wx, tx=0):
-    return {"diamond_width": dw, "cells_per_lane": vx, "threads_x": 64 * wx, "tile_x": tx}
+def mwd_params(dw, vx, wx, tx=0, nf=1):
+    return {"diamond_width": dw, "cells_per_lane": vx, "threads_x": 64 * wx, "tile_x": tx, "wavefront_depth": nf}
 
 
 @pytest.mark.parametrize("stencil,dtype,dw,vx,wx,tx,n,Ts", MWD_CASES)
@@ -148,6 +148,59 @@ def test_mwd_matches_naive_and_oracle_bitwise(stencil, dtype, dw, vx, wx, tx, n,
         assert_bitwise(got, naive, "mwd vs naive")
         if dtype == "f64":
             assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+# Wavefront depth N_F > 1 (NF planes per wavefront step): every compiled
+# variant on grids whose nz is odd and even, several x chunks, T below, at and
+# above the diamond height (stencil, dtype, Dw, cells per lane, waves along x,
+# N_F, tile_x or 0, grid, list of T)
+MWD_NF_CASES = [
+    ("7c", "f64", 8, 1, 2, 2, 0, (150, 45, 19), [1, 4, 5, 9, 13]),
+    ("7c", "f64", 8, 1, 2, 2, 0, (131, 50, 12), [7, 16]),
+    ("7c", "f32", 12, 1, 2, 2, 0, (131, 50, 13), [6, 7, 16]),
+    ("7c", "f32", 12, 1, 2, 2, 40, (131, 37, 8), [11]),
+    ("7c", "f32", 16, 1, 1, 2, 0, (70, 70, 9), [3, 8, 17]),
+    ("7c", "f32", 8, 1, 2, 2, 0, (150, 45, 20), [5, 9]),
+    ("25c", "f32", 16, 1, 1, 2, 0, (100, 45, 21), [1, 4, 7]),
+    ("25c", "f32", 16, 1, 1, 2, 0, (100, 45, 24), [2, 5]),
+    ("7v", "f64", 8, 1, 2, 2, 0, (129, 30, 15), [3, 7]),
+    ("7v", "f32", 8, 1, 2, 2, 0, (129, 30, 14), [4, 9]),
+]
+
+
+@pytest.mark.parametrize("stencil,dtype,dw,vx,wx,nf,tx,n,Ts", MWD_NF_CASES)
+def test_mwd_wavefront_depth_matches_naive_and_oracle_bitwise(stencil, dtype, dw, vx, wx, nf, tx, n, Ts):
+    u0, c, arr = inputs(stencil, *n, seed=13)
+    params = mwd_params(dw, vx, wx, tx, nf)
+    for T in Ts:
+        print("mwd nf", stencil, dtype, dw, vx, wx, nf, tx, n, T, flush=True)
+        got, info = run_gpu(stencil, dtype, u0, c, arr, T, algo="mwd", params=params)
+        q = info["params"]
+        assert (q["diamond_width"], q["cells_per_lane"], q["threads_x"], q["wavefront_depth"]) == (dw, vx, 64 * wx, nf)
+        ref = oracle_run(stencil, u0, c, arr, T, dtype)
+        assert_bitwise(got, ref, "mwd %s %s Dw=%d vx=%d wx=%d nf=%d T=%d" % (stencil, dtype, dw, vx, wx, nf, T))
+
+
+@pytest.mark.parametrize("stencil,dtype,dw,vx,wx,nf", [("7c", "f64", 8, 1, 2, 2), ("7c", "f32", 12, 1, 2, 2),
+                                                      ("25c", "f32", 16, 1, 1, 2)])
+def test_mwd_wavefront_depth_thin_and_nonzero_halo(stencil, dtype, dw, vx, wx, nf):
+    """Grids thinner than a slab or a diamond (nz = 1, 2, 3), and a nonzero
+    Dirichlet halo (with a -0.0), at N_F > 1."""
+    for n in ((9, 5, 1), (70, 3, 2), (33, 17, 3)):
+        u0, c, arr = inputs(stencil, *n, seed=14)
+        for T in (1, 5):
+            got, _ = run_gpu(stencil, dtype, u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx, 0, nf))
+            assert_bitwise(got, oracle_run(stencil, u0, c, arr, T, dtype), "thin %s nf=%d %s T=%d" % (stencil, nf, n, T))
+    u0, c, arr = inputs(stencil, 131, 29, 11, seed=8)
+    h = 1 if stencil.startswith("7") else 4
+    rng = np.random.default_rng(3)
+    halo = np.ones(u0.shape, dtype=bool)
+    halo[h:-h, h:-h, h:-h] = False
+    u0 = u0.copy()
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    u0[0, 0, 0] = -0.0
+    got, _ = run_gpu(stencil, dtype, u0, c, arr, 7, algo="mwd", params=mwd_params(dw, vx, wx, 0, nf))
+    assert_bitwise(got, oracle_run(stencil, u0, c, arr, 7, dtype), "nonzero halo %s nf=%d" % (stencil, nf))
 
 
 def test_mwd_T0_and_T1_and_tiny_grids():
@@ -320,28 +373,30 @@ def test_mwd_nonzero_halo(stencil, dw, vx, wx, n, T):
 
 
 def test_mwd_random_shapes_match_naive():
-    """Seeded random grids, step counts and registered blocked shapes (FP64
-    and FP32, both constant-coefficient stencils): the blocked sweep equals
-    the naive GPU sweep bit for bit, and every tenth case also the oracle."""
+    """Seeded random grids, step counts and registered blocked shapes, all
+    wavefront depths included (FP64 and FP32, both constant-coefficient
+    stencils): the blocked sweep equals the naive GPU sweep bit for bit, and
+    every tenth case also the oracle."""
     import paper_1510_04995_amd as P
     rng = np.random.default_rng(2024)
     shapes = {}
     for st in ("7c", "25c"):
         for dt in ("f64", "f32"):
             p = P.Sweep(st, dt, 64, 64, 64, [0.4, 0.1] if st == "7c" else [0.2, 0.05, 0.04, 0.03, 0.0133], "mwd")
-            shapes[(st, dt)] = sorted({(q["diamond_width"], q["cells_per_lane"], q["threads_x"] // 64)
-                                       for q in p.candidates()})
+            shapes[(st, dt)] = sorted({(q["diamond_width"], q["cells_per_lane"], q["threads_x"] // 64,
+                                        q["wavefront_depth"]) for q in p.candidates()})
             p.close()
     for case in range(120):
         st = ("7c", "25c")[case % 2]
         dt = ("f64", "f32")[(case // 2) % 2]
-        dw, vx, wx = shapes[(st, dt)][rng.integers(len(shapes[(st, dt)]))]
+        dw, vx, wx, nf = shapes[(st, dt)][rng.integers(len(shapes[(st, dt)]))]
         n = (int(rng.integers(1, 260)), int(rng.integers(1, 70)), int(rng.integers(1, 30)))
         T = int(rng.integers(0, 3 * dw))
-        print("random", case, st, dt, dw, vx, wx, n, T, flush=True)
+        print("random", case, st, dt, dw, vx, wx, nf, n, T, flush=True)
         u0, c, arr = inputs(st, *n, seed=case)
-        got, _ = run_gpu(st, dt, u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx))
+        got, _ = run_gpu(st, dt, u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx, 0, nf))
         naive, _ = run_gpu(st, dt, u0, c, arr, T, algo="naive")
-        assert_bitwise(got, naive, "random case %d %s %s Dw=%d vx=%d wx=%d n=%s T=%d" % (case, st, dt, dw, vx, wx, n, T))
+        assert_bitwise(got, naive, "random case %d %s %s Dw=%d vx=%d wx=%d nf=%d n=%s T=%d"
+                       % (case, st, dt, dw, vx, wx, nf, n, T))
         if case % 10 == 0:
             assert_bitwise(got, oracle_run(st, u0, c, arr, T, dt), "random case %d vs oracle" % case)

@@ -170,3 +170,21 @@ def test_plan_info_reports_the_papers_code_balance(stencil, dtype):
     G.girih_destroy(p)
     word = 8 if dtype == "f64" else 4
     assert bpl == pytest.approx(models.code_balance(params["diamond_width"], R, nd, word_bytes=word), rel=1e-12)
+
+
+def test_wavefront_depth_plans():
+    """N_F = 2 plans exist for the registered shapes: their stage holds two
+    planes per row, one buffer of 51 rows x 2 x 130 FP64 values for Dw = 8
+    and 128-cell rows -- the LDS that N_F = 1 spends on two stage buffers of
+    one plane -- and the candidate list of a problem offers both depths."""
+    g = grid(64)
+    p1 = G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 8, "threads_x": 128})
+    p2 = G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 8, "threads_x": 128, "wavefront_depth": 2})
+    q1, lds1, _ = G.girih_plan_info(p1)
+    q2, lds2, _ = G.girih_plan_info(p2)
+    assert q1["wavefront_depth"] == 1 and q2["wavefront_depth"] == 2
+    assert lds1 == lds2 == 51 * 2 * 130 * 8
+    depths = {q["wavefront_depth"] for q in G.girih_candidates(p1)}
+    assert depths == {1, 2}
+    G.girih_destroy(p1)
+    G.girih_destroy(p2)

@@ -122,12 +122,20 @@ def row_levels(R, DW, j, y, ny, t_c, T):
     lo, hi = max(b + 1, H - t_c), min(L - 1 - b, T - 1 + H - t_c)
     return (lo, hi) if lo <= hi else (1, 0)
 
-def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True):
-    H = DW // (2 * R); L = 2 * H; RING = 2 * R; NS = L + 2
-    UNR = RING if RING <= 2 else 1
-    nzs = nz + R * (L - 1)
-    zA = ((R * (L - 1) + UNR - 1) // UNR) * UNR
-    zB = max((nz // UNR) * UNR, zA)
+def kernel_steps(R, DW, nz, NF=1, UNR=None, PD=1):
+    """The wavefront steps of the kernel's three loops, as (zs, steady): zs
+    counts slabs of NF planes, from -2*RZ in blocks of UNR; steps [zA, zB) run
+    the steady body (mirrors mwd_tile)."""
+    H = DW // (2 * R); L = 2 * H
+    RZ = -(-R // NF); RING = 2 * RZ
+    UNR = UNR or RING
+    nzq = -(-nz // NF)
+    nzs = nzq + RZ * L
+    zA = -(-(RZ * L) // UNR) * UNR
+    zB1 = nz // NF
+    zB2 = (nz + R - NF) // NF - PD + 1
+    zB0 = min(zB1, zB2)
+    zB = max((zB0 // UNR) * UNR, zA)
     steps = []
     zb = -RING
     while zb < nzs:
@@ -137,6 +145,14 @@ def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True):
         steps += [(zb + p, True) for p in range(UNR)]; zb += UNR
     while zb < nzs:
         steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
+    return [(zs, st) for zs, st in steps if st or zs < nzs], RZ, nzq
+
+
+def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True, NF=1, UNR=None):
+    """Planes and rows of the coefficient and halo loads of both loop bodies,
+    for every wave of every diamond of every row, lie inside the haloed arrays."""
+    H = DW // (2 * R); L = 2 * H; NS = L + 2
+    steps, RZ, nzq = kernel_steps(R, DW, nz, NF, UNR)
     bad = []
     def chk(kind, q, y, info):
         if not (-R <= q < nz + R) or not (-R <= y < ny + R):
@@ -168,69 +184,70 @@ def load_bound_errors(R, DW, nx, ny, nz, T, ncoef, zh, fixed=True):
                     valid = (cmpB and t < nB) if isB else cmpA
                     k = (baseB if isB else baseA) + t
                     j = jB if isB else jA
-                    gos[s] = (L - k, ybase + j) if valid else (0, -R)   # (planes above the window's first, row); unused: 0, row -R
+                    # (slabs above the window's first, row); unused slots: 0, row -R
+                    gos[s] = (RZ * (L - k), ybase + j) if valid else (0, -R)
                     if valid and t >= 1: cm |= 1 << s
                 maskA = bit_range(0, sB - 1)
                 for zs, steady in steps:
-                    if not steady and zs >= nzs: continue
-                    zS = 0xffffffff
-                    if not steady:
-                        khz = zs // R if zs >= 0 else -1
-                        klz = (zs - nz) // R + 1 if zs - nz >= 0 else 0
-                        zS = (bit_range(klz - baseA, khz - baseA) & maskA) | (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA & 0xffffffff)
-                    for s in range(1, NS):
-                        zv = (((cm & zS) if fixed else zS) >> s) & 1
-                        dz, y = gos[s]
-                        if ncoef and (steady or zv):
-                            chk('coef', zs - R * L + R * dz, y, (r, m, side, dA, zs, steady, s))
-                        if not steady and not zv and not zh:
-                            isB = s >= sB
-                            k = baseB + (s - sB) if isB else baseA + s
-                            q = zs - R * k
-                            if (((cm >> s) & 1) or not fixed) and -R <= q < nz + R:
-                                chk('halo', q, ybase + (jB if isB else jA), (r, m, zs, s))
+                    for g in range(NF):
+                        zS = 0xffffffff
+                        if not steady:
+                            pz = NF * zs + g
+                            khz = pz // (NF * RZ) if pz >= 0 else -1
+                            klz = (pz - nz) // (NF * RZ) + 1 if pz - nz >= 0 else 0
+                            zS = (bit_range(klz - baseA, khz - baseA) & maskA) | (bit_range(klz - baseB + sB, khz - baseB + sB) & ~maskA & 0xffffffff)
+                        for s in range(1, NS):
+                            zv = (((cm & zS) if fixed else zS) >> s) & 1
+                            dz, y = gos[s]
+                            if ncoef and (steady or zv):
+                                chk('coef', NF * (zs - RZ * L + dz) + g, y, (r, m, side, dA, zs, steady, s, g))
+                            if not steady and not zv and not zh:
+                                isB = s >= sB
+                                k = baseB + (s - sB) if isB else baseA + s
+                                q = NF * (zs - RZ * k) + g
+                                if (((cm >> s) & 1) or not fixed) and -R <= q < nz + R:
+                                    chk('halo', q, ybase + (jB if isB else jA), (r, m, zs, s, g))
     return bad
 
 
 
-def check_prefetch(R, DW, ny, nz, T, PD=1, UNR=2):
+def check_prefetch(R, DW, ny, nz, T, PD=1, UNR=2, NF=1, steady_pd=None):
     """Planes of the prefetch loads (both bodies) stay inside [-R, nz+R); the
+    steady range holds only steps whose level planes and stored planes lie
+    inside the grid; every plane of the grid is stored once per level; the
     levels that rows computing nothing carry over (clipped-row kernel) are
     loaded for every plane of [0, nz) one step before the step that stores
-    them.  UNR: steps per loop iteration (2, or 2R where the kernel unrolls
-    every ring phase)."""
-    H = DW // (2 * R); L = 2 * H; RING = 2 * R
-    nzs = nz + R * L
-    zA = ((R * L + UNR - 1) // UNR) * UNR
-    zB0 = nz if R >= PD else nz + R - PD
-    zB = max((zB0 // UNR) * UNR, zA)
-    steps = []
-    zb = -RING
-    while zb < nzs:
-        if zA <= zb < zB: break
-        steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
-    while zb < zB:
-        steps += [(zb + p, True) for p in range(UNR)]; zb += UNR
-    while zb < nzs:
-        steps += [(zb + p, False) for p in range(UNR)]; zb += UNR
+    them.  UNR: steps per loop iteration (2, or 2*RZ where the kernel unrolls
+    every ring phase); NF: planes per step (slabs).  steady_pd: the prefetch
+    distance the steady range is computed for (default PD; another value
+    models a wrong range)."""
+    H = DW // (2 * R); L = 2 * H
+    steps, RZ, nzq = kernel_steps(R, DW, nz, NF, UNR, PD if steady_pd is None else steady_pd)
     bad = []
     dzs = set(range(0, L)) | {H}
     for zs, steady in steps:
-        if not steady and zs >= nzs: continue
-        for dz in dzs:
-            q = zs + PD - R * dz
-            if steady and not (-R <= q < nz + R):
-                bad.append((zs, dz, q))
         if steady:
+            for dz in dzs:
+                for g in range(NF):
+                    q = NF * (zs + PD - RZ * dz) + g
+                    if not (-R <= q < nz + R):
+                        bad.append((zs, dz, q))
             for k in range(L):
-                if not (0 <= zs - R * k < nz) or not (0 <= zs - R * (k + 1) < nz):
-                    bad.append(('plane', zs, k))
-    # carried levels: loaded at step zs for plane zs + PD, stored at step q = zs + PD
-    live = [zs for zs, steady in steps if steady or zs < nzs]
+                for g in range(NF):
+                    if not (0 <= NF * (zs - RZ * k) + g < nz) or not (0 <= NF * (zs - RZ * (k + 1)) + g < nz):
+                        bad.append(('plane', zs, k, g))
+    live = [zs for zs, steady in steps]
     if len(set(live)) != len(live) or live != sorted(live):
         bad.append(('step order', live[:5]))
-    loaded = {zs + PD for zs in live if 0 <= zs + PD < nz}
-    stored = {zs for zs in live if 0 <= zs < nz}
+    # stores: level k's stored slab at step zs is zs - RZ*(k+1); kept planes in [0, nz)
+    for k in range(L):
+        stored = [NF * (zs - RZ * (k + 1)) + g for zs in live for g in range(NF)]
+        kept = sorted(q for q in stored if 0 <= q < nz)
+        if kept != list(range(nz)):
+            bad.append(('stores', k, kept[:4]))
+    # carried levels: slab zs + PD loaded at step zs, stored at step zs + PD
+    loaded = {NF * (zs + PD) + g for zs in live for g in range(NF) if 0 <= NF * (zs + PD) + g < nz}
+    stored = {NF * zs + g for zs in live for g in range(NF) if 0 <= NF * zs + g < nz}
     if stored != set(range(nz)) or loaded != stored:
         bad.append(('carry', sorted(set(range(nz)) - stored)[:3], sorted(stored - loaded)[:3]))
     if steps and steps[0][0] % UNR != 0:
@@ -251,14 +268,30 @@ def test_every_stage_read_is_provided_once(R, DW):
             assert not e, (R, DW, ny, T, e[:3])
 
 
+NF_CONFIGS = [(1, 4, 2), (1, 8, 2), (1, 12, 2), (1, 16, 2), (4, 8, 2), (4, 16, 2), (4, 16, 4), (4, 8, 4), (1, 8, 3)]
+
+
 @pytest.mark.parametrize("R,DW", [(R, d) for R, ds in CONFIGS for d in ds if d <= 16])
 def test_loads_stay_inside_the_haloed_arrays(R, DW):
     for ny in (1, 3, 7, 2 * DW + 1):
         for nz in (1, 3, 9, 14):
             for T in (1, 3, 7):
                 for zh in (True, False):
-                    e = load_bound_errors(R, DW, 8, ny, nz, T, 1, zh)
-                    assert not e, (R, DW, ny, nz, T, zh, e[:2])
+                    for unr in sorted({2, 2 * R}):
+                        e = load_bound_errors(R, DW, 8, ny, nz, T, 1, zh, UNR=unr)
+                        assert not e, (R, DW, ny, nz, T, zh, unr, e[:2])
+
+
+@pytest.mark.parametrize("R,DW,NF", NF_CONFIGS)
+def test_loads_stay_inside_the_haloed_arrays_with_wavefront_depth(R, DW, NF):
+    RZ = -(-R // NF)
+    for ny in (1, 3, 2 * DW + 1):
+        for nz in (1, 2, 3, 5, 9, 14):
+            for T in (1, 3, 7):
+                for zh in (True, False):
+                    for unr in sorted({2, 2 * RZ}):
+                        e = load_bound_errors(R, DW, 8, ny, nz, T, 1, zh, NF=NF, UNR=unr)
+                        assert not e, (R, DW, NF, ny, nz, T, zh, unr, e[:2])
 
 
 def test_the_earlier_z_mask_is_caught():
@@ -273,6 +306,23 @@ def test_prefetch_planes_and_steady_range(R, DW):
         for nz in range(1, 40):
             e = check_prefetch(R, DW, 7, nz, 5, UNR=unr)
             assert not e, (R, DW, unr, nz, e[:3])
+
+
+@pytest.mark.parametrize("R,DW,NF", NF_CONFIGS)
+def test_prefetch_planes_and_steady_range_with_wavefront_depth(R, DW, NF):
+    RZ = -(-R // NF)
+    for unr in sorted({2, 2 * RZ}):
+        for nz in range(1, 40):
+            e = check_prefetch(R, DW, 7, nz, 5, UNR=unr, NF=NF)
+            assert not e, (R, DW, NF, unr, nz, e[:3])
+
+
+def test_a_steady_range_one_slab_too_long_is_caught():
+    # a steady range that ignored the loads of the next slab (as for a zero
+    # prefetch distance) would read past the haloed grid for NF = 2: the
+    # model flags it
+    assert any(check_prefetch(1, 8, 7, nz, 5, UNR=2, NF=2, steady_pd=0) for nz in range(2, 60))
+    assert not any(check_prefetch(1, 8, 7, nz, 5, UNR=2, NF=2) for nz in range(2, 60))
 
 
 def slots_needed(R, DW, t_c, T):
