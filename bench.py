@@ -300,7 +300,9 @@ def main():
     # roofline of the diamond-row kernel
     q = info["params"]
     H = q["diamond_width"] // (2 * h)
-    per_launch = launch_lups(w.nx, w.ny, w.nz, w.T, H)
+    # one launch per diamond row, or one dependency-driven launch per run
+    sweep_launch = q.get("variant", 0) == 1
+    per_launch = [float(w.lups)] if sweep_launch else launch_lups(w.nx, w.ny, w.nz, w.T, H)
     bpl = info["model_bytes_per_lup"]   # the paper's B_C for this plan
     alg_bytes_per_launch = bpl * sum(per_launch) / len(per_launch)
     avg_launch_s = kern_ms / max(n_launch, 1) * 1e-3
@@ -315,7 +317,8 @@ def main():
             traffic = prof.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "mwd_row_kernel", "bytes_per_lup_alg": round(bpl, 3),
+                "kernel": "mwd_sweep_kernel" if sweep_launch else "mwd_row_kernel",
+                "bytes_per_lup_alg": round(bpl, 3),
                 "x_halo_read_factor": round(x_halo_factor(q, h), 4),
                 "traffic_vs_alg": None if traffic is None else round(traffic / alg_bytes_per_launch, 3),
                 "lups_per_launch": round(sum(per_launch) / len(per_launch)), "launches": n_launch,

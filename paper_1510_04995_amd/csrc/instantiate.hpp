@@ -28,17 +28,30 @@ hipError_t launch_naive_tile(const void* args, dim3 grid, dim3 block, hipStream_
     return hipGetLastError();
 }
 
+template <class S, typename Real, int DW, int VX, int WX, int NF, int NSC>
+hipError_t launch_sweep(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
+    hipLaunchKernelGGL((mwd_sweep_kernel<S, Real, DW, VX, WX, NF, NSC>), grid, block, 0, stream,
+                       *static_cast<const MwdSweepArgs<Real>*>(args));
+    return hipGetLastError();
+}
+
 // A diamond shape registers its full kernel and, where it is smaller, the
 // kernel with H + 3 slots per wave: enough for the first diamond row (levels
 // below H lie before t = 0) and for the last one (levels from H on lie at or
 // after T).
-template <class S, typename Real, int DW, int VX, int WX, int NF = 1>
+// SWEEP: also compile the shape's dependency-driven whole-sweep kernel.
+template <class S, typename Real, int DW, int VX, int WX, int NF = 1, bool SWEEP = false>
 void add_mwd(std::vector<KernelEntry>& t, int st, int dt) {
     using K = MwdKernel<S, Real, DW, VX, WX, NF>;
     constexpr int H = K::H, L = K::L;
+    constexpr int NSC = H + 3 < L + 2 ? H + 3 : 0;
     t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0, 0, NF,
                             reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0, NF>),
                             &launch_mwd<S, Real, DW, VX, WX, 0, NF>});
+    if constexpr (SWEEP) {
+        t.back().sweep_func = reinterpret_cast<const void*>(&mwd_sweep_kernel<S, Real, DW, VX, WX, NF, NSC>);
+        t.back().launch_sweep = &launch_sweep<S, Real, DW, VX, WX, NF, NSC>;
+    }
     if constexpr (H + 3 < L + 2)
         t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3, 0, NF,
                                 reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3, NF>),
@@ -78,14 +91,15 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         // Variable coefficients: every slot also holds the byte offset of its
         // coefficient row, so fewer register slots fit than for the constant
         // stencil (Dw = 12 spills in FP64).
-        add_mwd<S, Real, 8, 1, 2>(t, st, dt);
+        // (shapes marked true also get the dependency-driven whole-sweep kernel)
+        add_mwd<S, Real, 8, 1, 2, 1, F64>(t, st, dt);
         add_mwd<S, Real, 8, 2, 1>(t, st, dt);
         add_mwd<S, Real, 8, 1, 2, 2>(t, st, dt);
         if constexpr (F64) {
             add_mwd<S, Real, 8, 1, 3>(t, st, dt);
         } else {
             add_mwd<S, Real, 8, 1, 4>(t, st, dt);
-            add_mwd<S, Real, 12, 1, 2>(t, st, dt);
+            add_mwd<S, Real, 12, 1, 2, 1, true>(t, st, dt);
             add_mwd<S, Real, 12, 2, 1>(t, st, dt);
             add_mwd<S, Real, 16, 1, 1>(t, st, dt);
         }
@@ -100,11 +114,11 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
     } else if constexpr (S::R == 1) {
         // (diamond width, cells per lane, waves along x)
         add_mwd<S, Real, 4, 2, 2>(t, st, dt);
-        add_mwd<S, Real, 8, 1, 2>(t, st, dt);
+        add_mwd<S, Real, 8, 1, 2, 1, true>(t, st, dt);
         add_mwd<S, Real, 8, 1, 3>(t, st, dt);
         add_mwd<S, Real, 8, 2, 1>(t, st, dt);
         add_mwd<S, Real, 8, 2, 2>(t, st, dt);
-        add_mwd<S, Real, 12, 1, 2>(t, st, dt);
+        add_mwd<S, Real, 12, 1, 2, 1, true>(t, st, dt);
         add_mwd<S, Real, 16, 1, 1>(t, st, dt);
         // wavefront depth 2 (two planes per step): twice the stage rows and
         // ring registers of depth 1
@@ -113,19 +127,19 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
             add_mwd<S, Real, 8, 1, 4>(t, st, dt);
             add_mwd<S, Real, 12, 2, 1>(t, st, dt);
             add_mwd<S, Real, 16, 2, 1>(t, st, dt);
-            add_mwd<S, Real, 12, 1, 2, 2>(t, st, dt);
+            add_mwd<S, Real, 12, 1, 2, 2, true>(t, st, dt);
             add_mwd<S, Real, 16, 1, 1, 2>(t, st, dt);
         }
     } else {
         add_mwd<S, Real, 8, 1, 2>(t, st, dt);
         add_mwd<S, Real, 8, 2, 1>(t, st, dt);
-        add_mwd<S, Real, 16, 1, 1>(t, st, dt);
+        add_mwd<S, Real, 16, 1, 1, 1, F64>(t, st, dt);
         if constexpr (!F64) {
             add_mwd<S, Real, 8, 1, 4>(t, st, dt);
             add_mwd<S, Real, 8, 2, 2>(t, st, dt);
-            add_mwd<S, Real, 16, 2, 1>(t, st, dt);
+            add_mwd<S, Real, 16, 2, 1, 1, true>(t, st, dt);
             add_mwd<S, Real, 24, 1, 1>(t, st, dt);
-            add_mwd<S, Real, 16, 1, 1, 2>(t, st, dt);
+            add_mwd<S, Real, 16, 1, 1, 2, true>(t, st, dt);
         }
     }
 }

@@ -311,8 +311,8 @@ enum : int {
 // does proportionally less work per step.  The host launches such a kernel
 // only for rows whose every wave fits (mwd_slots_needed).
 template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
-__device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk, const int diamond,
-                                         Real* __restrict__ stage) {
+__device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t row_t_c, const int chunk,
+                                         const int diamond, Real* __restrict__ stage) {
     using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP, RZ = KK::RZ;
@@ -353,7 +353,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int chunk
     const int x_own_lo = chunk * a.x_own;
     const int x_own_hi = x_own_lo + a.x_own < nx ? x_own_lo + a.x_own : nx;
     const int x0 = x_own_lo - KK::HX;              // x of column 0
-    const int t_c = (int)a.t_c, T = (int)a.T;
+    const int t_c = (int)row_t_c, T = (int)a.T;
 
     // per-lane constants: clamped byte offset within a row, ownership, x-halo
     uint32_t xb[VX], kill[VX];   // kill: DROP on lanes whose stores this chunk does not own
@@ -1094,6 +1094,110 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t launch_id, uint32_t 
     return (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
 }
 
+// Dependency-driven sweep (paper, Section "Runtime system": tiles are handed
+// to thread groups as their dependencies are met, with no barrier between
+// diamond rows).  One launch holds one workgroup per tile of every row, in
+// row order; within a row the tiles are numbered as in the row launches
+// (XCD-contiguous runs; each row's workgroups are padded to a multiple of
+// the XCD count, so a workgroup lands on the same XCD as in a row launch).
+// The hardware dispatches workgroups in launch order as compute units free
+// up; a tile then waits until the tiles of the previous row whose cells it
+// reads, or whose reads its stores would overwrite, are done: the two
+// diamonds of row r-1 over its rows and the x chunks within kx of its own.
+// Every tile a tile waits for comes earlier in the launch, so it has been
+// dispatched and waits only on tiles earlier still: the earliest unfinished
+// tile always runs, and the waits end.  They are bounded all the same: a
+// wait gives up after spin_limit polls (at once once another one has),
+// records the failure in *error for the host and lets the tile run, so
+// every workgroup exits.
+struct SweepSched {
+    uint32_t* done;        // completion marks: row r's tile u at [(r % 4) * tpr + u]
+    uint32_t* error;       // set nonzero when a wait gave up
+    uint32_t base;         // mark of a finished row-r tile: base + r + 1 (monotone across runs)
+    uint32_t spin_limit;   // polls before a wait gives up
+    int32_t n_chunks, tpr, kx, H;
+    int32_t nd[2];         // diamonds per row, by row parity
+    int32_t nb[2];         // workgroups per row (tiles padded to a multiple of 8), by row parity
+    int32_t clip_lo, clip_hi;   // rows outside [clip_lo, clip_hi) run the clipped-slot body
+};
+
+template <typename Real>
+struct MwdSweepArgs {
+    MwdArgs<Real> rows[2];   // the arguments of the even and of the odd rows (t_c aside)
+    SweepSched s;
+};
+
+template <class S, typename Real, int DW, int VX, int WX, int NF, int NSC>
+__global__ void __launch_bounds__(64 * (DW / 2) * WX)
+mwd_sweep_kernel(MwdSweepArgs<Real> sa) {
+    using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
+    __shared__ Real stage[KK::LDS_ROWS * KK::SROW];
+    const SweepSched& sc = sa.s;
+    // row and workgroup within the row (rows alternate two sizes)
+    const int bid = (int)blockIdx.x, two = sc.nb[0] + sc.nb[1];
+    const int rem = bid % two;
+    const int r = 2 * (bid / two) + (rem >= sc.nb[0] ? 1 : 0);
+    const int local = rem >= sc.nb[0] ? rem - sc.nb[0] : rem;
+    const int n_tiles = sc.nd[r & 1] * sc.n_chunks;
+    if (local >= n_tiles) return;   // padding
+    const int u = (int)xcd_contiguous((uint32_t)local, (uint32_t)n_tiles);
+    const int chunk = u % sc.n_chunks, diamond = u / sc.n_chunks;
+    if (threadIdx.x == 0 && r > 0) {
+        // row r-1's diamonds over this tile's rows: the row centres are
+        // offset by half a diamond, up for odd rows, down for even ones
+        const int m_lo = (r & 1) ? diamond : diamond - 1;
+        const int nd_prev = sc.nd[(r - 1) & 1];
+        const uint32_t want = sc.base + (uint32_t)r;   // mark of a finished row-(r-1) tile
+        const uint32_t* row_done = sc.done + ((r - 1) % 4) * sc.tpr;
+        uint32_t spins = 0;
+        for (int m = m_lo; m <= m_lo + 1; ++m) {
+            if (m < 0 || m >= nd_prev) continue;
+            for (int c = chunk - sc.kx; c <= chunk + sc.kx; ++c) {
+                if (c < 0 || c >= sc.n_chunks) continue;
+                const uint32_t* f = row_done + m * sc.n_chunks + c;
+                // relaxed device-scope polls read the mark from memory (not a
+                // stale L2 copy) without invalidating the caches each time
+                while ((int32_t)(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - want) < 0) {
+                    if (spins++ >= sc.spin_limit ||
+                        __hip_atomic_load(sc.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        __hip_atomic_store(sc.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+        }
+        // one acquire for all the marks read
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    // Thread 0's acquire invalidated the CU's and the XCD's caches,
+    // which all waves of the workgroup read through: after the barrier every
+    // wave sees what the tiles waited for wrote.  (One invalidation per tile:
+    // an acquire in every wave would also drop the cached data of the other
+    // tiles running on the XCD, a dozen times per tile.)
+    __syncthreads();
+    // (the arguments stay in the kernel's argument segment, where the
+    // compiler reloads them instead of holding them in registers)
+    const MwdArgs<Real>& a = sa.rows[r & 1];
+    const int64_t t_c = (int64_t)r * sc.H;
+    if constexpr (NSC > 0) {
+        if (r < sc.clip_lo || r >= sc.clip_hi)
+            mwd_tile<S, Real, DW, VX, WX, NSC, NF>(a, t_c, chunk, diamond, stage);
+        else
+            mwd_tile<S, Real, DW, VX, WX, 0, NF>(a, t_c, chunk, diamond, stage);
+    } else {
+        mwd_tile<S, Real, DW, VX, WX, 0, NF>(a, t_c, chunk, diamond, stage);
+    }
+    // The barrier waits until every wave's stores have reached the XCD's L2;
+    // thread 0's releasing store then writes the L2 back to memory before
+    // the mark, so the tile's results are visible device-wide once it is
+    // marked done.
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(sc.done + (r % 4) * sc.tpr + u, sc.base + (uint32_t)r + 1u, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One diamond row: one workgroup per (diamond, x-chunk) tile.
 template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
 __global__ void __launch_bounds__(64 * (DW / 2) * WX)
@@ -1101,7 +1205,7 @@ mwd_row_kernel(MwdArgs<Real> a) {
     using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
     __shared__ Real stage[KK::LDS_ROWS * KK::SROW];
     const uint32_t tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    mwd_tile<S, Real, DW, VX, WX, NSV, NF>(a, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage);
+    mwd_tile<S, Real, DW, VX, WX, NSV, NF>(a, a.t_c, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage);
 }
 
 }  // namespace girih

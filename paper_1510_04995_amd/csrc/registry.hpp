@@ -28,6 +28,10 @@ struct KernelEntry {
     int nf;          // MWD: wavefront depth (planes per wavefront step)
     const void* func;
     LaunchFn launch;
+    // MWD, full slot count: the dependency-driven whole-sweep kernel of the
+    // shape (one launch, persistent workgroups), or null where none is compiled
+    const void* sweep_func = nullptr;
+    LaunchFn launch_sweep = nullptr;
 };
 
 void register_kernels_7c_f64(std::vector<KernelEntry>&);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgirih.so")
 
 OK = 0
-E_INVALID, E_UNSUPPORTED, E_LDS, E_HIP, E_NOMEM, E_NOGPU, E_SCRATCH = -1, -2, -3, -4, -5, -6, -7
+E_INVALID, E_UNSUPPORTED, E_LDS, E_HIP, E_NOMEM, E_NOGPU, E_SCRATCH, E_STALL = -1, -2, -3, -4, -5, -6, -7, -8
 
 STENCIL_IDS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3, "25l": 4}
 DTYPE_IDS = {"f64": 0, "f32": 1}
@@ -88,6 +88,8 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "girih_plan_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams)]),
     "girih_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "girih_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "girih_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "girih_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "girih_destroy": (None, [ctypes.c_void_p]),
     "girih_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -255,6 +257,16 @@ def girih_plan_info(plan):
 def girih_plan_set_params(plan, params):
     p = params if isinstance(params, GirihParams) else GirihParams.from_dict(params)
     _check(_lib().girih_plan_set_params(plan, ctypes.byref(p)), "girih_plan_set_params")
+
+
+def girih_set_wait_limit(plan, polls):
+    _check(_lib().girih_set_wait_limit(plan, int(polls)), "girih_set_wait_limit")
+
+
+def girih_check(plan, stream_ptr):
+    """Synchronise the stream; GirihError(E_STALL) if a bounded dependency
+    wait of the plan's last variant-1 run gave up."""
+    _check(_lib().girih_check(plan, ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None), "girih_check")
 
 
 def girih_set_timing(plan, enable):

@@ -21,6 +21,13 @@ import json
 import sys
 
 ROW_KERNEL = "mwd_row_kernel"
+SWEEP_KERNEL = "mwd_sweep_kernel"
+
+
+def _kernel_of(b):
+    """Name stem of the bench line's dominant kernel (row launches or the
+    dependency-driven whole-sweep launch)."""
+    return b.get("roofline", {}).get("kernel", ROW_KERNEL)
 COPY_KERNEL = "copyBuffer"
 # MI355X: 256 CUs of 4 SIMDs in 8 XCDs; FP64 vector peak 78.6 TFLOP/s; LDS
 # 128 bytes per clock per CU
@@ -70,7 +77,7 @@ def stats(csv_path, bench_path, out_path, command):
     # bench.py's per-launch average covers all of them
     q = b["config"]["params"]
     key = _plan_key(b)
-    mine = [r for r in rows if ROW_KERNEL in r["Name"] and key in r["Name"]]
+    mine = [r for r in rows if _kernel_of(b) in r["Name"] and key in r["Name"]]
     calls = sum(int(r["Calls"]) for r in mine)
     tot_ns = sum(float(r["TotalDurationNs"]) for r in mine)
     rl = b["roofline"]
@@ -106,7 +113,7 @@ def traffic(fetch_csv, write_csv, bench_path, copy_mib, out_path, command):
         copies = sorted((i, v) for (k, i), v in d.items() if COPY_KERNEL in k)
         # the probe is the last copy of the run (bench.py issues it after the sweeps)
         probe = copies[-1][1] if copies else None
-        rows = [v for (k, _), v in d.items() if ROW_KERNEL in k]
+        rows = [v for (k, _), v in d.items() if _kernel_of(b) in k]
         scale = copy_kib / probe if probe else None
         mean_kib = sum(rows) / len(rows) if rows else None
         res[counter] = {"row_kernel_dispatches": len(rows), "row_kernel_mean_kib": mean_kib,
@@ -125,11 +132,11 @@ def traffic(fetch_csv, write_csv, bench_path, copy_mib, out_path, command):
         f.write("\n")
 
 
-def _row_kernel_means(path, key):
-    """{counter: mean over the plan's diamond-row dispatches of the per-dispatch sum}."""
+def _row_kernel_means(path, key, kernel=ROW_KERNEL):
+    """{counter: mean over the plan's dispatches of `kernel` of the per-dispatch sum}."""
     per = {}
     for r in csv.DictReader(open(path)):
-        if ROW_KERNEL not in r["Kernel_Name"] or key not in r["Kernel_Name"]:
+        if kernel not in r["Kernel_Name"] or key not in r["Kernel_Name"]:
             continue
         k = (r["Counter_Name"], int(r["Dispatch_Id"]))
         per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
@@ -144,8 +151,8 @@ def core(path_a, path_b, bench_path, out_path, command):
     b = _bench_line(bench_path)
     q = b["config"]["params"]
     key = _plan_key(b)
-    m = _row_kernel_means(path_a, key)
-    m.update({k: v for k, v in _row_kernel_means(path_b, key).items() if k not in m})
+    m = _row_kernel_means(path_a, key, _kernel_of(b))
+    m.update({k: v for k, v in _row_kernel_means(path_b, key, _kernel_of(b)).items() if k not in m})
     cyc = m["GRBM_GUI_ACTIVE"] / N_XCD              # kernel cycles (the counter sums the XCDs)
     ns = m["_ns"]
     clock_ghz = cyc / ns

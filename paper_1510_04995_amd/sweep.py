@@ -93,6 +93,16 @@ class Sweep:
         """(launches, total kernel milliseconds) of the most recent run."""
         return G.girih_timing(self.plan)
 
+    def check(self, stream=None):
+        """Synchronise; raise (E_STALL) if a dependency wait of the last
+        variant-1 run gave up."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        G.girih_check(self.plan, s.cuda_stream)
+
+    def set_wait_limit(self, polls):
+        G.girih_set_wait_limit(self.plan, polls)
+
     def set_params(self, params):
         G.girih_plan_set_params(self.plan, params)
 

@@ -203,6 +203,63 @@ def test_mwd_wavefront_depth_thin_and_nonzero_halo(stencil, dtype, dw, vx, wx, n
     assert_bitwise(got, oracle_run(stencil, u0, c, arr, 7, dtype), "nonzero halo %s nf=%d" % (stencil, nf))
 
 
+# Dependency-driven schedule (variant 1: one launch, each tile starts when
+# the tiles of the previous row it depends on are done): every shape compiled
+# with it, on grids with one and several x chunks and diamonds, T from one
+# row to many (stencil, dtype, Dw, cells per lane, waves along x, N_F,
+# tile_x or 0, grid, list of T)
+MWD_SWEEP_CASES = [
+    ("7c", "f64", 12, 1, 2, 1, 0, (300, 70, 17), [1, 5, 6, 7, 13, 40]),
+    ("7c", "f64", 12, 1, 2, 1, 40, (131, 50, 12), [9, 16]),
+    ("7c", "f64", 8, 1, 2, 1, 0, (150, 45, 19), [4, 9, 21]),
+    ("7c", "f32", 12, 1, 2, 1, 0, (200, 40, 11), [9, 16]),
+    ("7c", "f32", 12, 1, 2, 2, 0, (131, 50, 13), [6, 7, 30]),
+    ("25c", "f64", 16, 1, 1, 1, 0, (150, 50, 22), [2, 3, 5, 11]),
+    ("25c", "f32", 16, 2, 1, 1, 0, (260, 45, 17), [4, 9]),
+    ("25c", "f32", 16, 1, 1, 2, 0, (100, 45, 21), [1, 4, 7]),
+    ("7v", "f64", 8, 1, 2, 1, 0, (129, 30, 14), [3, 7, 12]),
+    ("7v", "f32", 12, 1, 2, 1, 0, (120, 41, 10), [6, 11]),
+]
+
+
+@pytest.mark.parametrize("stencil,dtype,dw,vx,wx,nf,tx,n,Ts", MWD_SWEEP_CASES)
+def test_mwd_dependency_driven_schedule_bitwise(stencil, dtype, dw, vx, wx, nf, tx, n, Ts):
+    u0, c, arr = inputs(stencil, *n, seed=17)
+    params = dict(mwd_params(dw, vx, wx, tx, nf), variant=1)
+    for T in Ts:
+        print("mwd sweep", stencil, dtype, dw, vx, wx, nf, tx, n, T, flush=True)
+        got, info = run_gpu(stencil, dtype, u0, c, arr, T, algo="mwd", params=params, check=True)
+        assert info["params"]["variant"] == 1
+        assert_bitwise(got, oracle_run(stencil, u0, c, arr, T, dtype),
+                       "sweep %s %s Dw=%d vx=%d wx=%d nf=%d T=%d" % (stencil, dtype, dw, vx, wx, nf, T))
+
+
+def test_dependency_waits_that_give_up_are_reported():
+    """With a wait limit of zero polls, tiles of the second and later rows give
+    up at once (every tile of this small grid is resident together), the
+    launch still ends and girih_check reports GIRIH_E_STALL; with the default
+    limit the same plan then computes the oracle's result."""
+    import paper_1510_04995_amd as P
+    import paper_1510_04995_amd.girih as G
+    from tests.gpu_util import torch_dev, upload
+    torch, dev = torch_dev()
+    n = (150, 60, 40)
+    u0, c, arr = inputs("7c", *n, seed=18)
+    sw = P.Sweep("7c", "f64", *n, list(c), "mwd", {"diamond_width": 12, "threads_x": 128, "variant": 1})
+    sw.set_wait_limit(0)
+    b0, b1 = upload(u0), upload(u0)
+    sw.run(b0, b1, 30)
+    with pytest.raises(G.GirihError) as e:
+        sw.check()
+    assert e.value.code == G.E_STALL
+    sw.set_wait_limit(1 << 20)
+    b0, b1 = upload(u0), upload(u0)
+    out = sw.run(b0, b1, 30)
+    sw.check()
+    assert_bitwise(out.cpu().numpy(), oracle_run("7c", u0, c, arr, 30), "after a stalled run")
+    sw.close()
+
+
 def test_mwd_T0_and_T1_and_tiny_grids():
     for n in ((1, 1, 1), (3, 2, 5), (9, 1, 4), (2, 17, 1)):
         u0, c, arr = inputs("7c", *n, seed=4)
@@ -281,6 +338,32 @@ def test_small_workload_exact():
     for algo in ("naive", "mwd"):
         got, _ = run_gpu(w.stencil, "f64", u0, c, arr, w.T, algo=algo)
         assert_bitwise(got, ref, "64^3 %s vs oracle" % algo)
+
+
+@pytest.mark.parametrize("stencil,dtype,params", [("7c", "f64", {"variant": 1}),
+                                                  ("7c", "f64", {"variant": 1, "diamond_width": 12, "threads_x": 128,
+                                                                 "tile_x": 86}),
+                                                  ("25c", "f64", {"variant": 1})])
+def test_full_size_dependency_driven(stencil, dtype, params):
+    """512^3 (T = 64 for 7-point, 32 for 25-point) with the dependency-driven
+    schedule, default shape (and, for 7-point, six x chunks per row): the
+    whole grid equals the oracle."""
+    import paper_1510_04995_amd as P
+    from tests.gpu_util import torch_dev
+    from workloads import WORKLOADS
+    torch, dev = torch_dev()
+    w = WORKLOADS["7pt-const-512" if stencil == "7c" else "25pt-const-512"]
+    u0, c, arr = inputs(w.stencil, w.nx, w.ny, w.nz, seed=0)
+    g0 = torch.from_numpy(u0).to(dev)
+    sw = P.Sweep(w.stencil, dtype, w.nx, w.ny, w.nz, [float(x) for x in c], "mwd", params)
+    b0, b1 = g0.clone(), g0.clone()
+    print("full size sweep", stencil, dtype, params, flush=True)
+    out = sw.run(b0, b1, w.T)
+    sw.check()
+    got = out.cpu().numpy()
+    sw.close()
+    del b0, b1, g0, out
+    assert_bitwise(got, oracle_run(w.stencil, u0, c, arr, w.T), "full size sweep %s %s" % (stencil, params))
 
 
 @pytest.mark.parametrize("stencil,dtype,n,T", [("7c", "f64", (509, 511, 513), 63), ("7c", "f32", (509, 511, 513), 63),

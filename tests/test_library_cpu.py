@@ -188,3 +188,22 @@ def test_wavefront_depth_plans():
     assert depths == {1, 2}
     G.girih_destroy(p1)
     G.girih_destroy(p2)
+
+
+def test_schedule_variant_plans():
+    """variant 1 (the dependency-driven schedule) exists for the shapes
+    compiled with it and is offered among the candidates; other shapes
+    refuse it, and unknown variants are invalid."""
+    g = grid(64)
+    p = G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"variant": 1})
+    q, _, _ = G.girih_plan_info(p)
+    assert q["variant"] == 1 and q["diamond_width"] == 12
+    assert {c["variant"] for c in G.girih_candidates(p)} == {0, 1}
+    G.girih_destroy(p)
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 8, "cells_per_lane": 2, "threads_x": 64,
+                                                         "variant": 1})
+    assert e.value.code == G.E_UNSUPPORTED
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"variant": 2})
+    assert e.value.code == G.E_INVALID
