@@ -46,7 +46,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 WORKLOAD = "7pt-const-512"
-STENCIL_NAMES = {"7c": "7-point constant (c0=0.4, c1=0.1)", "25c": "25-point constant (c0..c4 drawn, normalised)"}
+STENCIL_NAMES = {"7c": "7-point constant (c0=0.4, c1=0.1)", "25c": "25-point constant (c0..c4 drawn, normalised)",
+                 "7v": "7-point variable (7 coefficient arrays)", "25v": "25-point variable (13 coefficient arrays)"}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "mwd_7pt_const_512_f64_traffic.txt")
 KERNEL_SOURCES = ("paper_1510_04995_amd/csrc/mwd.hpp", "paper_1510_04995_amd/csrc/stencils.hpp",
                   "paper_1510_04995_amd/csrc/kernels_7c_f64.hip", "paper_1510_04995_amd/csrc/instantiate.hpp")
@@ -237,7 +238,9 @@ def main():
     ap.add_argument("--no-suite", action="store_true", help="skip the other workloads (per_stencil)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="workload of the timed runs (default: the headline 7-point constant 512^3; another "
-                         "constant-coefficient workload serves profiling runs of its blocked kernel)")
+                         "first-order workload serves profiling runs of its blocked kernel)")
+    ap.add_argument("--dtype", default="f64", choices=("f64", "f32"),
+                    help="element type of the timed runs (FP64 unless profiling the FP32 kernels)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -256,20 +259,26 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     w = WORKLOADS[args.workload]
-    if w.stencil not in ("7c", "25c"):
-        print("--workload takes a constant-coefficient workload", file=sys.stderr)
+    if w.stencil not in ("7c", "25c", "7v", "25v"):
+        print("--workload takes a first-order workload (the blocked sweep's)", file=sys.stderr)
+        sys.exit(2)
+    if args.dtype != "f64" and (not args.no_compare or not args.no_cpu):
+        print("--dtype f32 is for profiling runs (with --no-compare --no-cpu)", file=sys.stderr)
         sys.exit(2)
     h = w.radius
-    u0, c, _ = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
-    g0 = torch.from_numpy(u0).to(dev)
+    u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    g0 = torch.from_numpy(u0).to(dev).to(tdt)
+    coefs = [torch.from_numpy(a).to(dev).to(tdt) for a in (arr or [])]
+    cl = None if c is None else list(c)
     params = json.loads(args.params) if args.params else None
 
-    sw = P.Sweep(w.stencil, "f64", w.nx, w.ny, w.nz, list(c), "mwd", params)
+    sw = P.Sweep(w.stencil, args.dtype, w.nx, w.ny, w.nz, cl, "mwd", params)
     info = sw.info()
     b0, b1 = g0.clone(), g0.clone()
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        sw.run(b0, b1, w.T)
+        sw.run(b0, b1, w.T, coefs)
     torch.cuda.synchronize()
 
     sw.set_timing(True)
@@ -282,7 +291,7 @@ def main():
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        sw.run(b0, b1, w.T)
+        sw.run(b0, b1, w.T, coefs)
         ev1.record(stream)
         ev1.synchronize()
         times.append(ev0.elapsed_time(ev1) * 1e-3)
@@ -301,7 +310,7 @@ def main():
     q = info["params"]
     H = q["diamond_width"] // (2 * h)
     # one launch per diamond row, or one dependency-driven launch per run
-    sweep_launch = q.get("variant", 0) == 1
+    sweep_launch = (q.get("variant", 0) & 1) == 1
     per_launch = [float(w.lups)] if sweep_launch else launch_lups(w.nx, w.ny, w.nz, w.T, H)
     bpl = info["model_bytes_per_lup"]   # the paper's B_C for this plan
     alg_bytes_per_launch = bpl * sum(per_launch) / len(per_launch)
@@ -327,29 +336,30 @@ def main():
     compare = None
     if not args.no_compare:
         compare = {}
-        nv = P.Sweep(w.stencil, "f64", w.nx, w.ny, w.nz, list(c), "naive")
+        nv = P.Sweep(w.stencil, "f64", w.nx, w.ny, w.nz, cl, "naive")
         n0, n1 = g0.clone(), g0.clone()
-        nv.run(n0, n1, w.T)
+        nv.run(n0, n1, w.T, coefs)
         torch.cuda.synchronize()
         t = time.perf_counter()
         reps = 3
         for _ in range(reps):
-            ref = nv.run(n0, n1, w.T)
+            ref = nv.run(n0, n1, w.T, coefs)
         torch.cuda.synchronize()
         compare["naive_f64_glups"] = round(lups * reps / (time.perf_counter() - t) / 1e9, 2)
         # bit-exactness of the blocked run on the same input
         m0, m1 = g0.clone(), g0.clone()
-        res64 = sw.run(m0, m1, w.T)
+        res64 = sw.run(m0, m1, w.T, coefs)
         r0, r1 = g0.clone(), g0.clone()
-        ref = nv.run(r0, r1, w.T)
+        ref = nv.run(r0, r1, w.T, coefs)
         rel, mx, nd = P.error_norms(res64, ref, h, w.nx, w.ny, w.nz)
         compare["blocked_vs_naive_f64_bitwise_diff"] = nd
         nv.close()
         del n0, n1, r0, r1
-        s32 = P.Sweep(w.stencil, "f32", w.nx, w.ny, w.nz, list(c), "mwd")
+        s32 = P.Sweep(w.stencil, "f32", w.nx, w.ny, w.nz, cl, "mwd")
         g32 = g0.to(torch.float32)
+        c32 = [a.to(torch.float32) for a in coefs]
         f0, f1 = g32.clone(), g32.clone()
-        s32.run(f0, f1, w.T)
+        s32.run(f0, f1, w.T, c32)
         best = None
         for _ in range(reps):
             # fresh input each time: the last run's result is the FP32 answer for u0
@@ -357,7 +367,7 @@ def main():
             f1.copy_(g32)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            res32 = s32.run(f0, f1, w.T)
+            res32 = s32.run(f0, f1, w.T, c32)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             best = dt if best is None else min(best, dt)
@@ -387,7 +397,7 @@ def main():
         a0 = u0.copy()
         a1 = u0.copy()
         t = time.perf_counter()
-        O.sweep(w.stencil, a0, a1, 2, c, None)
+        O.sweep(w.stencil, a0, a1, 2, c, arr)
         rate = w.nx * w.ny * w.nz * 2 / (time.perf_counter() - t)
         # about ten seconds of oracle time: the whole run when it is shorter
         # (repeated, continuing in time), else part of it
@@ -395,7 +405,7 @@ def main():
         a0 = u0.copy()
         a1 = u0.copy()
         t = time.perf_counter()
-        O.sweep(w.stencil, a0, a1, t_s, c, None)
+        O.sweep(w.stencil, a0, a1, t_s, c, arr)
         dt = time.perf_counter() - t
         what = ("%d of the %d steps" % (t_s, w.T) if t_s < w.T else
                 "%d steps (the %d-step run %.1f times over)" % (t_s, w.T, t_s / w.T))
@@ -411,7 +421,7 @@ def main():
             a0 = u0.copy()
             a1 = u0.copy()
             t = time.perf_counter()
-            O.sweep(w.stencil, a0, a1, t1, c, None)
+            O.sweep(w.stencil, a0, a1, t1, c, arr)
             dt1 = time.perf_counter() - t
         finally:
             O.set_num_threads(n_all)
@@ -432,7 +442,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "stencil": STENCIL_NAMES[w.stencil], "stencil_id": w.stencil,
                    "grid": [w.nx, w.ny, w.nz], "halo": h, "T": w.T, "algo": "mwd", "params": q,

@@ -42,7 +42,7 @@ extern "C" {
 #define GIRIH_E_NOMEM (-5)       /* device or host allocation failed */
 #define GIRIH_E_NOGPU (-6)       /* no usable gfx950 device */
 #define GIRIH_E_SCRATCH (-7)     /* grid larger than girih_run_noalloc's fixed scratch */
-#define GIRIH_E_STALL (-8)       /* a bounded dependency wait of variant 1 gave up (girih_check) */
+#define GIRIH_E_STALL (-8)       /* a bounded device wait of variants 1-3 gave up (girih_check) */
 
 /* Stencils (paper Listings 1-4; the 25-point constant stencil is the
  * first-order Jacobi form of Listing 3's bracketed term, the leapfrog one is
@@ -88,15 +88,19 @@ typedef struct girih_grid {
  *                        cells, owned tile plus the recomputed halo;
  *         threads_y      row pairs = waves along y (filled in: Dw/2);
  *         tile_y, tile_z filled in: Dw and nz;
- *         variant        schedule of the diamond rows (paper, Section
- *                        "Runtime system"): 0 = one launch per row (the
- *                        stream orders the rows); 1 = one launch of
- *                        persistent workgroups that take tiles from per-XCD
- *                        queues and start each as soon as the tiles of the
- *                        previous row it depends on are done (shapes
- *                        compiled with it, girih_candidates).  A tile always
- *                        synchronises its waves with a barrier per
- *                        wavefront step.
+ *         variant        two bits.  Bit 0, schedule of the diamond rows
+ *                        (paper, Section "Runtime system"): 0 = one launch
+ *                        per row (the stream orders the rows); 1 = one
+ *                        launch of a workgroup per tile of every row, in
+ *                        row order, each tile starting once the tiles of
+ *                        the previous row it depends on are done.  Bit 1,
+ *                        synchronisation of the waves of a tile (paper,
+ *                        Section "Multi-core wavefront temporal blocking"):
+ *                        0 = workgroup barriers in every wavefront step;
+ *                        1 = relaxed: each wave waits only for the waves
+ *                        whose stage rows it reads or that read its own.
+ *                        Either bit needs a shape compiled with it
+ *                        (girih_candidates lists them).
  *  NAIVE: variant        0 = x/y neighbours through the caches (any block
  *                        of at most 256 threads, threads_x a multiple of 64),
  *                        1 = each plane's x/y neighbourhood staged in an LDS
@@ -159,18 +163,20 @@ int girih_run(girih_plan_t plan, void* buf0, void* buf1, const void* const* coef
  *  is shared by every call on that device: calls that overlap on one device
  *  (other streams, other threads) race and must be serialised by the caller.
  *  Nothing in it needs to start at zero (each run initialises what it
- *  reads).  Plans of variant 1 run with one launch per diamond row here (the
- *  fixed array has no room for the schedule's completion marks). */
+ *  reads).  Plans with variant bit 0 set run with one launch per diamond
+ *  row here (the fixed array has no room for the schedule's completion
+ *  marks). */
 int girih_run_noalloc(girih_plan_t plan, void* buf0, void* buf1, const void* const* coef_arrays, int32_t n_coef,
                       int64_t T, void* hip_stream, int32_t* result_index);
 
-/* Variant-1 runs (the dependency-driven schedule) wait on the device for the
- * tiles a tile depends on.  The waits cannot deadlock (tiles are handed out
- * in row order), and each is bounded anyway: after `polls` polls (default
- * 2^20, about a second) a wait gives up, records the failure and lets its
- * tile run, so the launch always ends; the result is then wrong.
+/* Runs of variants 1-3 wait on the device: the dependency-driven schedule
+ * for the tiles a tile depends on, relaxed synchronisation for the waves of
+ * a tile.  The waits cannot deadlock (tiles start in row order; a wave waits
+ * only on earlier phases of other waves), and each is bounded anyway: after
+ * `polls` polls (default 2^20) a wait gives up, records the failure and
+ * goes on, so the launch always ends; the result is then wrong.
  * girih_check synchronises hip_stream and returns GIRIH_E_STALL if a wait of
- * the plan's last variant-1 run gave up, GIRIH_OK otherwise. */
+ * the plan's last run gave up, GIRIH_OK otherwise. */
 int girih_set_wait_limit(girih_plan_t plan, uint32_t polls);
 int girih_check(girih_plan_t plan, void* hip_stream);
 

@@ -14,7 +14,7 @@ All arithmetic of the network (forward, back-propagation, Adam) runs in the
 features, the parameter initialisation and the training loop, with PyTorch
 providing device memory and the stream.
 
-Features of a candidate (16, in this order):
+Features of a candidate (20, in this order):
   0 stencil radius R          1 number of coefficient arrays
   2-4 log2 nx, ny, nz          5 dtype (0 = FP64, 1 = FP32)
   6 diamond width Dw           7 wavefront depth N_F
@@ -22,7 +22,15 @@ Features of a candidate (16, in this order):
   10 log2 z tile               11 threads along x / 64 (waves along x)
   12 threads along y (row pairs)  13 x cells per lane
   14 LDS bytes / 64 KiB        15 log2 T
-They are standardised with the mean and spread of the training set.
+  16 schedule (variant bit 0: dependency-driven)
+  17 synchronisation (variant bit 1: relaxed)
+  18 log2 of the paper's blocked code balance B_C (bytes per update,
+     Section "Memory traffic model"; N_D = 2 + coefficient arrays)
+  19 log2 of the redundant x-halo read factor (x tile + 2R(L-1)) / x tile
+They are standardised with the mean and spread of the training set.  The
+last two carry the traffic model across stencils: a problem whose
+coefficient arrays the training set never saw still differs from the
+training problems in B_C, which the training set relates to throughput.
 """
 import math
 
@@ -30,19 +38,26 @@ import numpy as np
 
 from . import girih as G
 
-N_FEATURES = 16
+N_FEATURES = 20
 STENCIL_NCOEF = G.N_COEF
 RADIUS = G.RADIUS
 
 
 def features(stencil, dtype, nx, ny, nz, T, params, lds_bytes):
-    """The 16 raw features of one candidate (see the module docstring)."""
+    """The 20 raw features of one candidate (see the module docstring)."""
     q = params
+    v = int(q.get("variant") or 0)
+    R, dw, tx = RADIUS[stencil], float(q["diamond_width"]), float(max(1, q["tile_x"]))
+    s = 8.0 if dtype == "f64" else 4.0
+    nd = 2 + STENCIL_NCOEF[stencil]
+    b_c = 2 * s * R * ((2 * dw - 2 * R) + (nd * dw + 2 * R)) / (dw * dw)
+    rho = (tx + 2 * R * (dw / R - 1)) / tx
     return [float(RADIUS[stencil]), float(STENCIL_NCOEF[stencil]), math.log2(nx), math.log2(ny), math.log2(nz),
             0.0 if dtype == "f64" else 1.0, float(q["diamond_width"]), float(q["wavefront_depth"] or 1),
             math.log2(max(1, q["tile_x"])), float(q["tile_y"]), math.log2(max(1, q["tile_z"])),
             q["threads_x"] / 64.0, float(q["threads_y"]), float(q.get("cells_per_lane") or 1),
-            lds_bytes / 65536.0, math.log2(max(1, T))]
+            lds_bytes / 65536.0, math.log2(max(1, T)), float(v & 1), float((v >> 1) & 1), math.log2(b_c),
+            math.log2(rho)]
 
 
 def candidate_table(sweep, T):
@@ -88,7 +103,7 @@ def he_uniform(n_in, n_hidden, n_layers, seed=0):
 
 
 class CostModel:
-    """A 16 -> n_layers x n_hidden (ReLU) -> 1 network predicting log GLUP/s."""
+    """A 20 -> n_layers x n_hidden (ReLU) -> 1 network predicting log GLUP/s."""
 
     def __init__(self, n_hidden=64, n_layers=3, seed=0, device=None):
         import torch

@@ -7,9 +7,9 @@
 
 namespace girih {
 
-template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
+template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF, int SY>
 hipError_t launch_mwd(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
-    hipLaunchKernelGGL((mwd_row_kernel<S, Real, DW, VX, WX, NSV, NF>), grid, block, 0, stream,
+    hipLaunchKernelGGL((mwd_row_kernel<S, Real, DW, VX, WX, NSV, NF, SY>), grid, block, 0, stream,
                        *static_cast<const MwdArgs<Real>*>(args));
     return hipGetLastError();
 }
@@ -28,9 +28,9 @@ hipError_t launch_naive_tile(const void* args, dim3 grid, dim3 block, hipStream_
     return hipGetLastError();
 }
 
-template <class S, typename Real, int DW, int VX, int WX, int NF, int NSC>
+template <class S, typename Real, int DW, int VX, int WX, int NF, int NSC, int SY>
 hipError_t launch_sweep(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
-    hipLaunchKernelGGL((mwd_sweep_kernel<S, Real, DW, VX, WX, NF, NSC>), grid, block, 0, stream,
+    hipLaunchKernelGGL((mwd_sweep_kernel<S, Real, DW, VX, WX, NF, NSC, SY>), grid, block, 0, stream,
                        *static_cast<const MwdSweepArgs<Real>*>(args));
     return hipGetLastError();
 }
@@ -40,22 +40,28 @@ hipError_t launch_sweep(const void* args, dim3 grid, dim3 block, hipStream_t str
 // below H lie before t = 0) and for the last one (levels from H on lie at or
 // after T).
 // SWEEP: also compile the shape's dependency-driven whole-sweep kernel.
-template <class S, typename Real, int DW, int VX, int WX, int NF = 1, bool SWEEP = false>
+// SY: relaxed synchronisation within the tile (per-wave step counters
+// instead of workgroup barriers).
+template <class S, typename Real, int DW, int VX, int WX, int NF = 1, bool SWEEP = false, int SY = 0>
 void add_mwd(std::vector<KernelEntry>& t, int st, int dt) {
     using K = MwdKernel<S, Real, DW, VX, WX, NF>;
     constexpr int H = K::H, L = K::L;
     constexpr int NSC = H + 3 < L + 2 ? H + 3 : 0;
-    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, 0, 0, NF,
-                            reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0, NF>),
-                            &launch_mwd<S, Real, DW, VX, WX, 0, NF>});
+    constexpr int LDS = K::LDS_BYTES + (SY ? 128 : 0);
+    t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, LDS, K::XOWN_MAX, 0, 0, NF,
+                            reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, 0, NF, SY>),
+                            &launch_mwd<S, Real, DW, VX, WX, 0, NF, SY>});
+    t.back().sync = SY;
     if constexpr (SWEEP) {
-        t.back().sweep_func = reinterpret_cast<const void*>(&mwd_sweep_kernel<S, Real, DW, VX, WX, NF, NSC>);
-        t.back().launch_sweep = &launch_sweep<S, Real, DW, VX, WX, NF, NSC>;
+        t.back().sweep_func = reinterpret_cast<const void*>(&mwd_sweep_kernel<S, Real, DW, VX, WX, NF, NSC, SY>);
+        t.back().launch_sweep = &launch_sweep<S, Real, DW, VX, WX, NF, NSC, SY>;
     }
-    if constexpr (H + 3 < L + 2)
-        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, K::LDS_BYTES, K::XOWN_MAX, H + 3, 0, NF,
-                                reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3, NF>),
-                                &launch_mwd<S, Real, DW, VX, WX, H + 3, NF>});
+    if constexpr (H + 3 < L + 2) {
+        t.push_back(KernelEntry{st, dt, AL_MWD, DW, VX, WX, K::NT, LDS, K::XOWN_MAX, H + 3, 0, NF,
+                                reinterpret_cast<const void*>(&mwd_row_kernel<S, Real, DW, VX, WX, H + 3, NF, SY>),
+                                &launch_mwd<S, Real, DW, VX, WX, H + 3, NF, SY>});
+        t.back().sync = SY;
+    }
 }
 
 template <class S, typename Real, int BY>
@@ -120,6 +126,8 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
         add_mwd<S, Real, 8, 2, 2>(t, st, dt);
         add_mwd<S, Real, 12, 1, 2, 1, true>(t, st, dt);
         add_mwd<S, Real, 16, 1, 1>(t, st, dt);
+        // relaxed synchronisation within the tile
+        add_mwd<S, Real, 12, 1, 2, 1, true, 1>(t, st, dt);
         // wavefront depth 2 (two planes per step): twice the stage rows and
         // ring registers of depth 1
         add_mwd<S, Real, 8, 1, 2, 2>(t, st, dt);
@@ -129,6 +137,7 @@ void add_family(std::vector<KernelEntry>& t, int st, int dt) {
             add_mwd<S, Real, 16, 2, 1>(t, st, dt);
             add_mwd<S, Real, 12, 1, 2, 2, true>(t, st, dt);
             add_mwd<S, Real, 16, 1, 1, 2>(t, st, dt);
+            add_mwd<S, Real, 12, 1, 2, 2, true, 1>(t, st, dt);
         }
     } else {
         add_mwd<S, Real, 8, 1, 2>(t, st, dt);

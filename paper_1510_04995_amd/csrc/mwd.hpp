@@ -111,6 +111,10 @@ struct MwdArgs {
     int64_t t_c;         // row centre time: row r has t_c = r*H
     int64_t c_first;     // y centre of the row's first diamond
     int32_t x_own;       // x cells stored by one workgroup
+    // relaxed synchronisation within a tile: a wait on the waves of the
+    // workgroup gives up after spin_limit polls and sets *error (nonzero)
+    uint32_t* error;
+    uint32_t spin_limit;
 };
 
 template <int R_, int DW_>
@@ -148,6 +152,62 @@ __host__ __device__ inline int partner_of(int d) {
     const int b = d / Sh::R, e = d % Sh::R;
     const int b2 = Sh::H - 1 - b;
     return b2 != b ? b2 * Sh::R + e : b * Sh::R + (e ^ 1);
+}
+
+// The two rows of row pair pw (0 .. DW/2-1): pairs 0 .. DW/4-1 take the
+// right half of the diamond (j >= DW/2), the others the left half; within a
+// half, pair p takes the p-th half-distance d (in increasing order) that is
+// smaller than its partner, and that partner.
+template <class Sh>
+__host__ __device__ inline void pair_rows(int pw, int& dA, int& dB, int& jA, int& jB) {
+    const int per_side = Sh::DW / 4;
+    const int side = pw / per_side;   // 0: right half, 1: left half
+    int p = pw % per_side;
+    dA = dB = 0;
+    for (int d = 0; d < Sh::DW / 2; ++d) {
+        const int pd = partner_of<Sh>(d);
+        if (d < pd) {
+            if (p == 0) { dA = d; dB = pd; }
+            --p;
+        }
+    }
+    jA = side == 0 ? Sh::DW / 2 + dA : Sh::DW / 2 - 1 - dA;
+    jB = side == 0 ? Sh::DW / 2 + dB : Sh::DW / 2 - 1 - dB;
+}
+
+// Waves of a workgroup whose stage rows a wave of row pair pw reads, or which
+// read its stage rows (level k+1 of a row reads level k of the rows within R
+// of it; a wave stages its two rows and, for a row in the outermost block of
+// R rows, the row R beyond it), plus the waves of the same row pair (other x
+// slices, whose edge cells it reads): one bit per wave w, pair w % npairs.
+template <class Sh>
+__host__ __device__ inline uint32_t pair_neighbours(int pw, int npairs, int nwaves) {
+    constexpr int R = Sh::R, H = Sh::H, DW = Sh::DW;
+    auto rows = [](int q, int (&j)[4]) {
+        int dA, dB;
+        pair_rows<Sh>(q, dA, dB, j[0], j[1]);
+        const int sgn = q / (DW / 4) == 0 ? 1 : -1;
+        j[2] = dA / R == H - 1 ? j[0] + sgn * R : -1000;
+        j[3] = dB / R == H - 1 ? j[1] + sgn * R : -1000;
+    };
+    int mine[4];
+    rows(pw, mine);
+    uint32_t pairs = 0;   // bit per row pair
+    for (int q = 0; q < npairs; ++q) {
+        int th[4];
+        rows(q, th);
+        bool near = q == pw;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 4; ++v) {
+                const int d1 = mine[u] - th[v], d2 = th[u] - mine[v];
+                near = near || (d1 >= -R && d1 <= R) || (d2 >= -R && d2 <= R);
+            }
+        if (near) pairs |= 1u << q;
+    }
+    uint32_t waves = 0;
+    for (int w = 0; w < nwaves; ++w)
+        if ((pairs >> (w % npairs)) & 1u) waves |= 1u << w;
+    return waves;
 }
 
 // Level range [kf, kl] computed at local row j whose global row is y
@@ -310,9 +370,20 @@ enum : int {
 // of the run clips hold fewer slots per wave, and a kernel with fewer slots
 // does proportionally less work per step.  The host launches such a kernel
 // only for rows whose every wave fits (mwd_slots_needed).
-template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
+//
+// SY = 1: relaxed synchronisation (paper, Section "Multi-core wavefront
+// temporal blocking": each thread waits only for the threads whose data it
+// uses).  The two workgroup barriers of a step become waits on per-wave step
+// counters in LDS: a wave stages step zs once the waves that read its stage
+// rows have finished step zs-1 (zs-2 with two stage buffers), and updates
+// once the waves whose rows it reads have staged step zs, so a wave that is
+// ahead overlaps its staging with the update of waves that are behind.
+// (Zero-halo instance only; the general-halo instance stages halo rows for
+// other waves and keeps the barriers.)
+template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF, int SY = 0>
 __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t row_t_c, const int chunk,
-                                         const int diamond, Real* __restrict__ stage) {
+                                         const int diamond, Real* __restrict__ stage,
+                                         uint32_t* __restrict__ sync_flags = nullptr) {
     using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
     using Sh = typename KK::Sh;
     constexpr int R = S::R, H = Sh::H, L = Sh::L, RING = KK::RING, XLP = KK::XLP, RZ = KK::RZ;
@@ -378,19 +449,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
     }
 
     // ---- this wave's two rows ------------------------------------------------
-    const int per_side = DW / 4;
-    const int side = pw / per_side;         // 0: right half (j >= DW/2), 1: left half
-    int p = pw % per_side;
-    int dA = 0, dB = 0;
-    for (int d = 0; d < DW / 2; ++d) {
-        const int pd = partner_of<Sh>(d);
-        if (d < pd) {
-            if (p == 0) { dA = d; dB = pd; }
-            --p;
-        }
-    }
-    const int jA = side == 0 ? DW / 2 + dA : DW / 2 - 1 - dA;
-    const int jB = side == 0 ? DW / 2 + dB : DW / 2 - 1 - dB;
+    const int side = pw / (DW / 4);         // 0: right half (j >= DW/2), 1: left half
+    int dA, dB, jA, jB;
+    pair_rows<Sh>(pw, dA, dB, jA, jB);
     int kfA, klA, kfB, klB;
     row_levels<Sh>(jA, ybase + jA, ny, t_c, T, kfA, klA);
     row_levels<Sh>(jB, ybase + jB, ny, t_c, T, kfB, klB);
@@ -518,6 +579,47 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
     // constants) and general halo (loaded where needed).
     auto sweep = [&](auto zhc) __attribute__((always_inline)) {
         constexpr bool ZH = decltype(zhc)::value;
+        // relaxed synchronisation: per-wave counters of staged (sync_flags[w])
+        // and updated (sync_flags[16 + w]) steps; step zs counts as zs + RING + 1
+        constexpr bool RLX = SY != 0 && ZH;
+        static_assert(SY == 0 || KK::NWAVES <= 16, "step counters for at most 16 waves");
+        const uint32_t nbr = RLX ? pair_neighbours<Sh>(pw, KK::NPAIRS, KK::NWAVES) & ~(1u << wave) : 0u;
+        bool gave_up = false;
+        if constexpr (RLX) {
+            if (threadIdx.x < 32) sync_flags[threadIdx.x] = 0u;
+        }
+        // counter of step zs in bank b (0: staged, 1: updated) of this wave
+        auto post = [&](int b, int zs) __attribute__((always_inline)) {
+            // the wave's LDS writes (b = 0) or reads (b = 1) of the step are
+            // complete before the counter moves
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0)
+                __hip_atomic_store(sync_flags + 16 * b + wave, (uint32_t)(zs + RING + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        // wait until every neighbour's counter in bank b has reached step zs
+        auto wait = [&](int b, int zs) __attribute__((always_inline)) {
+            if (gave_up) return;
+            const uint32_t want = (uint32_t)(zs + RING + 1);
+            uint32_t spins = 0;
+            for (;;) {
+                // lane l reads wave l % 16's counter
+                const uint32_t c = __hip_atomic_load(sync_flags + 16 * b + (lane & 15), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint64_t behind = __ballot((int32_t)(c - want) < 0) & (uint64_t)nbr;
+                if (behind == 0) break;
+                if (spins++ >= a.spin_limit) {
+                    // cannot happen while every wave runs (each waits only on
+                    // counters of earlier phases); bounded all the same
+                    gave_up = true;
+                    if (lane == 0) __hip_atomic_store(a.error, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                // (no sleep between polls: a wave waits a phase of a neighbour
+                // at most, and a sleep would add its length to every wait)
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        };
         // Halo rows of the stage (rows outside the grid, inside it +-R): with a zero
         // halo they are written once here and never touched again.
         if (ZH && edge_y) {
@@ -669,6 +771,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
             for (int f = 0; f < NF; ++f)
 #pragma unroll
                 for (int v = 0; v < VX; ++v) { vcA[f][v] = qA[ph % PD][f][v]; vcB[f][v] = qB[ph % PD][f][v]; }
+            // the readers of this wave's stage rows are done with the buffer
+            if constexpr (RLX) wait(1, zs - (KK::DB ? 2 : 1));
             // ---- A: stage every plane the levels read this step ------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
@@ -770,7 +874,12 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                     }
                 }
             }
-            __syncthreads();
+            if constexpr (RLX) {
+                post(0, zs);
+                wait(0, zs);
+            } else {
+                __syncthreads();
+            }
             // ---- B: update every (row, level) slot of this step ----------------------
             if (live) {
                 const int f = (int)fresh_s((uint32_t)flags);
@@ -1019,7 +1128,10 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                     }
                 }
             }
-            if constexpr (!KK::DB) __syncthreads();   // with two buffers the next step's staging may overlap
+            if constexpr (RLX)
+                post(1, zs);
+            else if constexpr (!KK::DB)
+                __syncthreads();   // with two buffers the next step's staging may overlap
         };
 
         // the sweep starts 2*RZ steps early so that the input rings of rows
@@ -1127,11 +1239,12 @@ struct MwdSweepArgs {
     SweepSched s;
 };
 
-template <class S, typename Real, int DW, int VX, int WX, int NF, int NSC>
+template <class S, typename Real, int DW, int VX, int WX, int NF, int NSC, int SY = 0>
 __global__ void __launch_bounds__(64 * (DW / 2) * WX)
 mwd_sweep_kernel(MwdSweepArgs<Real> sa) {
     using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
     __shared__ Real stage[KK::LDS_ROWS * KK::SROW];
+    __shared__ uint32_t sync_flags[SY ? 32 : 1];
     const SweepSched& sc = sa.s;
     // row and workgroup within the row (rows alternate two sizes)
     const int bid = (int)blockIdx.x, two = sc.nb[0] + sc.nb[1];
@@ -1182,11 +1295,11 @@ mwd_sweep_kernel(MwdSweepArgs<Real> sa) {
     const int64_t t_c = (int64_t)r * sc.H;
     if constexpr (NSC > 0) {
         if (r < sc.clip_lo || r >= sc.clip_hi)
-            mwd_tile<S, Real, DW, VX, WX, NSC, NF>(a, t_c, chunk, diamond, stage);
+            mwd_tile<S, Real, DW, VX, WX, NSC, NF, SY>(a, t_c, chunk, diamond, stage, sync_flags);
         else
-            mwd_tile<S, Real, DW, VX, WX, 0, NF>(a, t_c, chunk, diamond, stage);
+            mwd_tile<S, Real, DW, VX, WX, 0, NF, SY>(a, t_c, chunk, diamond, stage, sync_flags);
     } else {
-        mwd_tile<S, Real, DW, VX, WX, 0, NF>(a, t_c, chunk, diamond, stage);
+        mwd_tile<S, Real, DW, VX, WX, 0, NF, SY>(a, t_c, chunk, diamond, stage, sync_flags);
     }
     // The barrier waits until every wave's stores have reached the XCD's L2;
     // thread 0's releasing store then writes the L2 back to memory before
@@ -1199,13 +1312,15 @@ mwd_sweep_kernel(MwdSweepArgs<Real> sa) {
 }
 
 // One diamond row: one workgroup per (diamond, x-chunk) tile.
-template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF>
+template <class S, typename Real, int DW, int VX, int WX, int NSV, int NF, int SY = 0>
 __global__ void __launch_bounds__(64 * (DW / 2) * WX)
 mwd_row_kernel(MwdArgs<Real> a) {
     using KK = MwdKernel<S, Real, DW, VX, WX, NF>;
     __shared__ Real stage[KK::LDS_ROWS * KK::SROW];
+    __shared__ uint32_t sync_flags[SY ? 32 : 1];
     const uint32_t tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    mwd_tile<S, Real, DW, VX, WX, NSV, NF>(a, a.t_c, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage);
+    mwd_tile<S, Real, DW, VX, WX, NSV, NF, SY>(a, a.t_c, (int)(tile % gridDim.x), (int)(tile / gridDim.x), stage,
+                                               sync_flags);
 }
 
 }  // namespace girih

@@ -32,6 +32,9 @@ struct KernelEntry {
     // shape (one launch, persistent workgroups), or null where none is compiled
     const void* sweep_func = nullptr;
     LaunchFn launch_sweep = nullptr;
+    // MWD: 0 = workgroup barriers between the phases of a wavefront step,
+    // 1 = relaxed synchronisation (per-wave step counters in LDS)
+    int sync = 0;
 };
 
 void register_kernels_7c_f64(std::vector<KernelEntry>&);

@@ -264,8 +264,8 @@ def girih_set_wait_limit(plan, polls):
 
 
 def girih_check(plan, stream_ptr):
-    """Synchronise the stream; GirihError(E_STALL) if a bounded dependency
-    wait of the plan's last variant-1 run gave up."""
+    """Synchronise the stream; GirihError(E_STALL) if a bounded device wait
+    of the plan's last run (variants 1-3) gave up."""
     _check(_lib().girih_check(plan, ctypes.c_void_p(int(stream_ptr)) if stream_ptr else None), "girih_check")
 
 

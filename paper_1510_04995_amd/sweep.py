@@ -94,8 +94,8 @@ class Sweep:
         return G.girih_timing(self.plan)
 
     def check(self, stream=None):
-        """Synchronise; raise (E_STALL) if a dependency wait of the last
-        variant-1 run gave up."""
+        """Synchronise; raise (E_STALL) if a bounded device wait of the last
+        run (variants 1-3) gave up."""
         import torch
         s = stream if stream is not None else torch.cuda.current_stream()
         G.girih_check(self.plan, s.cuda_stream)

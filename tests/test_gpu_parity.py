@@ -234,6 +234,73 @@ def test_mwd_dependency_driven_schedule_bitwise(stencil, dtype, dw, vx, wx, nf, 
                        "sweep %s %s Dw=%d vx=%d wx=%d nf=%d T=%d" % (stencil, dtype, dw, vx, wx, nf, T))
 
 
+# Relaxed synchronisation within the tile (variant bit 1: per-wave step
+# counters instead of barriers), with row launches (2) and with the
+# dependency-driven schedule (3), for every shape compiled with it; the
+# non-zero halo case runs the general-halo instance, which keeps the barriers.
+MWD_RELAX_CASES = [
+    ("7c", "f64", 12, 1, 2, 1, 0, (300, 70, 17), [1, 5, 6, 7, 13, 40]),
+    ("7c", "f64", 12, 1, 2, 1, 40, (131, 50, 12), [9, 16]),
+    ("7c", "f64", 12, 1, 2, 1, 0, (70, 13, 5), [3, 12]),
+    ("7c", "f32", 12, 1, 2, 2, 0, (131, 50, 13), [6, 7, 30]),
+    ("7c", "f32", 12, 1, 2, 2, 0, (260, 37, 9), [1, 11]),
+]
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("stencil,dtype,dw,vx,wx,nf,tx,n,Ts", MWD_RELAX_CASES)
+def test_mwd_relaxed_synchronisation_bitwise(stencil, dtype, dw, vx, wx, nf, tx, n, Ts, variant):
+    u0, c, arr = inputs(stencil, *n, seed=19)
+    params = dict(mwd_params(dw, vx, wx, tx, nf), variant=variant)
+    for T in Ts:
+        print("mwd relaxed", variant, stencil, dtype, dw, vx, wx, nf, tx, n, T, flush=True)
+        got, info = run_gpu(stencil, dtype, u0, c, arr, T, algo="mwd", params=params, check=True)
+        assert info["params"]["variant"] == variant
+        assert_bitwise(got, oracle_run(stencil, u0, c, arr, T, dtype),
+                       "relaxed v%d %s %s Dw=%d nf=%d T=%d" % (variant, stencil, dtype, dw, nf, T))
+
+
+@pytest.mark.parametrize("dtype,nf", [("f64", 1), ("f32", 2)])
+def test_mwd_relaxed_synchronisation_nonzero_halo(dtype, nf):
+    n = (90, 40, 15)
+    u0, c, arr = inputs("7c", *n, seed=20)
+    rng = np.random.default_rng(20)
+    halo = np.ones(u0.shape, bool)
+    halo[1:-1, 1:-1, 1:-1] = False
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    params = dict(mwd_params(12, 1, 2, 0, nf), variant=2)
+    print("mwd relaxed nonzero halo", dtype, nf, flush=True)
+    got, _ = run_gpu("7c", dtype, u0, c, arr, 9, algo="mwd", params=params, check=True)
+    assert_bitwise(got, oracle_run("7c", u0, c, arr, 9, dtype), "relaxed nonzero halo %s" % dtype)
+
+
+def test_relaxed_waits_that_give_up_are_reported():
+    """A wait limit of zero polls makes a wave give up at its first wait that
+    finds a neighbour behind (among the many waits of a 30-step run some
+    do): the launch ends, girih_check reports GIRIH_E_STALL, and with the
+    default limit the plan then computes the oracle's result."""
+    import paper_1510_04995_amd as P
+    import paper_1510_04995_amd.girih as G
+    from tests.gpu_util import torch_dev, upload
+    torch, dev = torch_dev()
+    n = (150, 60, 40)
+    u0, c, arr = inputs("7c", *n, seed=21)
+    sw = P.Sweep("7c", "f64", *n, list(c), "mwd", {"variant": 2})
+    sw.set_wait_limit(0)
+    b0, b1 = upload(u0), upload(u0)
+    print("relaxed stall", flush=True)
+    sw.run(b0, b1, 30)
+    with pytest.raises(G.GirihError) as e:
+        sw.check()
+    assert e.value.code == G.E_STALL
+    sw.set_wait_limit(1 << 20)
+    b0, b1 = upload(u0), upload(u0)
+    out = sw.run(b0, b1, 30)
+    sw.check()
+    assert_bitwise(out.cpu().numpy(), oracle_run("7c", u0, c, arr, 30), "after a stalled relaxed run")
+    sw.close()
+
+
 def test_dependency_waits_that_give_up_are_reported():
     """With a wait limit of zero polls, tiles of the second and later rows give
     up at once (every tile of this small grid is resident together), the
@@ -343,18 +410,22 @@ def test_small_workload_exact():
 @pytest.mark.parametrize("stencil,dtype,params", [("7c", "f64", {"variant": 1}),
                                                   ("7c", "f64", {"variant": 1, "diamond_width": 12, "threads_x": 128,
                                                                  "tile_x": 86}),
-                                                  ("25c", "f64", {"variant": 1})])
+                                                  ("25c", "f64", {"variant": 1}),
+                                                  ("7c", "f64", {"variant": 2}),
+                                                  ("7c", "f64", {"variant": 3}),
+                                                  ("7c", "f32", {"variant": 2})])
 def test_full_size_dependency_driven(stencil, dtype, params):
     """512^3 (T = 64 for 7-point, 32 for 25-point) with the dependency-driven
-    schedule, default shape (and, for 7-point, six x chunks per row): the
-    whole grid equals the oracle."""
+    schedule, default shape (and, for 7-point, six x chunks per row), and
+    with relaxed synchronisation: the whole grid equals the oracle (of the
+    plan's precision)."""
     import paper_1510_04995_amd as P
     from tests.gpu_util import torch_dev
     from workloads import WORKLOADS
     torch, dev = torch_dev()
     w = WORKLOADS["7pt-const-512" if stencil == "7c" else "25pt-const-512"]
     u0, c, arr = inputs(w.stencil, w.nx, w.ny, w.nz, seed=0)
-    g0 = torch.from_numpy(u0).to(dev)
+    g0 = torch.from_numpy(u0.astype(np.float64 if dtype == "f64" else np.float32)).to(dev)
     sw = P.Sweep(w.stencil, dtype, w.nx, w.ny, w.nz, [float(x) for x in c], "mwd", params)
     b0, b1 = g0.clone(), g0.clone()
     print("full size sweep", stencil, dtype, params, flush=True)
@@ -363,7 +434,8 @@ def test_full_size_dependency_driven(stencil, dtype, params):
     got = out.cpu().numpy()
     sw.close()
     del b0, b1, g0, out
-    assert_bitwise(got, oracle_run(w.stencil, u0, c, arr, w.T), "full size sweep %s %s" % (stencil, params))
+    assert_bitwise(got, oracle_run(w.stencil, u0, c, arr, w.T, dtype), "full size sweep %s %s %s"
+                   % (stencil, dtype, params))
 
 
 @pytest.mark.parametrize("stencil,dtype,n,T", [("7c", "f64", (509, 511, 513), 63), ("7c", "f32", (509, 511, 513), 63),
@@ -467,19 +539,20 @@ def test_mwd_random_shapes_match_naive():
         for dt in ("f64", "f32"):
             p = P.Sweep(st, dt, 64, 64, 64, [0.4, 0.1] if st == "7c" else [0.2, 0.05, 0.04, 0.03, 0.0133], "mwd")
             shapes[(st, dt)] = sorted({(q["diamond_width"], q["cells_per_lane"], q["threads_x"] // 64,
-                                        q["wavefront_depth"]) for q in p.candidates()})
+                                        q["wavefront_depth"], q["variant"]) for q in p.candidates()})
             p.close()
     for case in range(120):
         st = ("7c", "25c")[case % 2]
         dt = ("f64", "f32")[(case // 2) % 2]
-        dw, vx, wx, nf = shapes[(st, dt)][rng.integers(len(shapes[(st, dt)]))]
+        dw, vx, wx, nf, var = shapes[(st, dt)][rng.integers(len(shapes[(st, dt)]))]
         n = (int(rng.integers(1, 260)), int(rng.integers(1, 70)), int(rng.integers(1, 30)))
         T = int(rng.integers(0, 3 * dw))
-        print("random", case, st, dt, dw, vx, wx, nf, n, T, flush=True)
+        print("random", case, st, dt, dw, vx, wx, nf, var, n, T, flush=True)
         u0, c, arr = inputs(st, *n, seed=case)
-        got, _ = run_gpu(st, dt, u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx, 0, nf))
+        got, _ = run_gpu(st, dt, u0, c, arr, T, algo="mwd", params=dict(mwd_params(dw, vx, wx, 0, nf), variant=var),
+                         check=var != 0)
         naive, _ = run_gpu(st, dt, u0, c, arr, T, algo="naive")
-        assert_bitwise(got, naive, "random case %d %s %s Dw=%d vx=%d wx=%d nf=%d n=%s T=%d"
-                       % (case, st, dt, dw, vx, wx, nf, n, T))
+        assert_bitwise(got, naive, "random case %d %s %s Dw=%d vx=%d wx=%d nf=%d variant=%d n=%s T=%d"
+                       % (case, st, dt, dw, vx, wx, nf, var, n, T))
         if case % 10 == 0:
             assert_bitwise(got, oracle_run(st, u0, c, arr, T, dt), "random case %d vs oracle" % case)

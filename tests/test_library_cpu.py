@@ -95,7 +95,7 @@ def test_mwd_variable_coefficient_shapes():
     """Blocked plans of the variable-coefficient stencils exist for the
     registered (spill-free) shapes only; the second-order-in-time stencil has
     none."""
-    for st, h, dt, dw in (("7v", 1, "f64", 8), ("7v", 1, "f32", 12), ("25v", 4, "f64", 8), ("25v", 4, "f32", 16)):
+    for st, h, dt, dw in (("7v", 1, "f64", 8), ("7v", 1, "f32", 8), ("25v", 4, "f64", 8), ("25v", 4, "f32", 16)):
         p = G.girih_plan(st, dt, grid(h=h), None, "mwd")
         assert G.girih_plan_info(p)[0]["diamond_width"] == dw
         G.girih_destroy(p)
@@ -191,19 +191,30 @@ def test_wavefront_depth_plans():
 
 
 def test_schedule_variant_plans():
-    """variant 1 (the dependency-driven schedule) exists for the shapes
-    compiled with it and is offered among the candidates; other shapes
-    refuse it, and unknown variants are invalid."""
+    """Variant bit 0 (the dependency-driven schedule) and bit 1 (relaxed
+    synchronisation) exist for the shapes compiled with them and are offered
+    among the candidates; other shapes refuse them, and values beyond the two
+    bits are invalid."""
     g = grid(64)
-    p = G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"variant": 1})
+    for v in (1, 2, 3):
+        p = G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"variant": v})
+        q, lds, _ = G.girih_plan_info(p)
+        assert q["variant"] == v and q["diamond_width"] == 12
+        # the relaxed kernels keep 32 step counters beside the stage
+        assert lds == (103088 if v & 2 else 102960)
+        assert {c["variant"] for c in G.girih_candidates(p)} == {0, 1, 2, 3}
+        G.girih_destroy(p)
+    for v in (1, 2):
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 8, "cells_per_lane": 2,
+                                                             "threads_x": 64, "variant": v})
+        assert e.value.code == G.E_UNSUPPORTED
+    for v in (4, -1):
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"variant": v})
+        assert e.value.code == G.E_INVALID
+    # FP32 7-point: the default shape (two planes per step) has both bits
+    p = G.girih_plan("7c", "f32", g, (0.4, 0.1), "mwd", {"variant": 3})
     q, _, _ = G.girih_plan_info(p)
-    assert q["variant"] == 1 and q["diamond_width"] == 12
-    assert {c["variant"] for c in G.girih_candidates(p)} == {0, 1}
+    assert q["wavefront_depth"] == 2 and q["diamond_width"] == 12
     G.girih_destroy(p)
-    with pytest.raises(G.GirihError) as e:
-        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"diamond_width": 8, "cells_per_lane": 2, "threads_x": 64,
-                                                         "variant": 1})
-    assert e.value.code == G.E_UNSUPPORTED
-    with pytest.raises(G.GirihError) as e:
-        G.girih_plan("7c", "f64", g, (0.4, 0.1), "mwd", {"variant": 2})
-    assert e.value.code == G.E_INVALID
