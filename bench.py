@@ -26,7 +26,8 @@ Beside the headline value the line carries:
   compare       naive GPU sweep (FP64), blocked FP32 run and its error against
                 the FP64 result, measured outside the timed region;
   per_stencil   every other workload of the study (25-point constant 512^3,
-                25-point variable 384^3, 7-point variable 256x512x1024), blocked
+                25-point variable 384^3, 7-point variable 256x512x1024, the
+                second-order 25-point stencil on 512^3), blocked
                 and naive, FP64 and FP32, timed the same way outside the timed
                 region, with the FP32 error against the FP64 blocked result
                 (which equals the FP64 oracle bit for bit, as the GPU parity
@@ -47,7 +48,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 WORKLOAD = "7pt-const-512"
 STENCIL_NAMES = {"7c": "7-point constant (c0=0.4, c1=0.1)", "25c": "25-point constant (c0..c4 drawn, normalised)",
-                 "7v": "7-point variable (7 coefficient arrays)", "25v": "25-point variable (13 coefficient arrays)"}
+                 "7v": "7-point variable (7 coefficient arrays)", "25v": "25-point variable (13 coefficient arrays)",
+                 "25l": "25-point second order in time (c0..c4, C array)"}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "mwd_7pt_const_512_f64_traffic.txt")
 KERNEL_SOURCES = ("paper_1510_04995_amd/csrc/mwd.hpp", "paper_1510_04995_amd/csrc/stencils.hpp",
                   "paper_1510_04995_amd/csrc/kernels_7c_f64.hip", "paper_1510_04995_amd/csrc/instantiate.hpp")
@@ -159,7 +161,7 @@ def per_stencil(torch, dev, reps=3):
     import paper_1510_04995_amd as P
     from workloads import WORKLOADS, field_and_coefs
     res = {}
-    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024"):
+    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512"):
         w = WORKLOADS[name]
         h = w.radius
         log("inputs " + name)
@@ -208,7 +210,7 @@ def oracle_rates(O, seconds=4.0):
     """The oracle on the other workloads: a few steps each on all threads."""
     from workloads import WORKLOADS, field_and_coefs
     out = {}
-    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024"):
+    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512"):
         w = WORKLOADS[name]
         log("oracle " + name)
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0)
@@ -259,8 +261,8 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     w = WORKLOADS[args.workload]
-    if w.stencil not in ("7c", "25c", "7v", "25v"):
-        print("--workload takes a first-order workload (the blocked sweep's)", file=sys.stderr)
+    if w.stencil not in ("7c", "25c", "7v", "25v", "25l"):
+        print("unknown stencil of workload %s" % w.name, file=sys.stderr)
         sys.exit(2)
     if args.dtype != "f64" and (not args.no_compare or not args.no_cpu):
         print("--dtype f32 is for profiling runs (with --no-compare --no-cpu)", file=sys.stderr)

@@ -64,9 +64,10 @@ typedef enum {
     GIRIH_NAIVE = 0, /* T launches of one full-domain Jacobi step              */
     GIRIH_MWD = 1    /* diamond rows: one launch per row of diamond tiles      */
 } girih_algo;
-/* This version provides GIRIH_MWD for the first-order constant-coefficient
- * stencils (GIRIH_7PT_CONST, GIRIH_25PT_CONST); girih_plan returns
- * GIRIH_E_UNSUPPORTED for GIRIH_MWD with the other stencils. */
+/* GIRIH_MWD exists for every stencil, in the diamond shapes compiled for it
+ * (girih_candidates); girih_plan returns GIRIH_E_UNSUPPORTED for a shape
+ * that was not compiled.  For the second-order-in-time stencil a level also
+ * reads the level two below it at its own cell. */
 
 /* Grid descriptor, in elements. */
 typedef struct girih_grid {
@@ -256,8 +257,10 @@ int girih_tune_log(girih_plan_t plan, girih_tune_record* out, int32_t cap, int32
  * balance in bytes per lattice update: for MWD the paper's blocked code
  * balance B_C (Section "Memory traffic model", both equations, scaled to the
  * element size: 2 * size * R * [(2Dw - 2R) + (N_D*Dw + 2R)] / Dw^2, with N_D
- * the domain-sized streams); the redundant x-halo that x-chunking reads on
- * top of it is not included; for NAIVE the streaming (2 + n_coef) * size. */
+ * = 2 + n_coef domain-sized streams read); the redundant x-halo that
+ * x-chunking reads on top of it is not included; for NAIVE the streaming
+ * (2 + n_coef) * size, plus one more stream (u^{t-1}) for the
+ * second-order-in-time stencil. */
 int girih_plan_info(girih_plan_t plan, girih_params* params, int64_t* lds_bytes, double* model_bytes_per_lup);
 
 /* Change the parameters of an existing plan (validated like girih_plan). */

@@ -90,9 +90,13 @@ template <class S, typename Real>
 void add_family(std::vector<KernelEntry>& t, int st, int dt) {
     add_naive<S, Real>(t, st, dt);
     constexpr bool F64 = sizeof(Real) == 8;
-    // The second-order-in-time stencil has a naive sweep only: its blocked
-    // form needs a third time level per diamond cell.
+    // The second-order-in-time stencil: a level also reads the level two
+    // below at its own cell (from the ring two slots back, or for a row's
+    // first level from HBM) and its C array like a coefficient array.
     if constexpr (S::LEAPFROG) {
+        add_mwd<S, Real, 16, 1, 1, 1, F64>(t, st, dt);
+        add_mwd<S, Real, 8, 1, 2>(t, st, dt);
+        if constexpr (!F64) add_mwd<S, Real, 16, 1, 1, 2>(t, st, dt);
     } else if constexpr (S::NCOEF > 0 && S::R == 1) {
         // Variable coefficients: every slot also holds the byte offset of its
         // coefficient row, so fewer register slots fit than for the constant

@@ -513,6 +513,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
     auto fo_of = [&](int dz, int j) -> uint32_t { return (uint32_t)(NF * RZ * (L - dz)) * plane_b + rowb_of(j); };
     const uint32_t uA2 = (uint32_t)(lds_row(kvA - 1, jA) * SB), uB2 = (uint32_t)(lds_row(kvB - 1, jB) * SB),
                    uOA = (uint32_t)(lds_row(H - 1, joA) * SB), uOB = (uint32_t)(lds_row(H - 1, joB) * SB);
+    // second-order-in-time stencils: the first level kf of a computing row
+    // also reads level kf-2 (time t-1) at its own cell, slab zs - RZ*kf
+    const uint32_t foUA = fo_of(kvA + 1 < L ? kvA + 1 : 0, jA), foUB = fo_of(kvB + 1 < L ? kvB + 1 : 0, jB);
     const uint32_t foA = fo_of(kvA < 0 ? 0 : kvA, jA), foB = fo_of(kvB < 0 ? 0 : kvB, jB),
                    foOA = fo_of(H, joA > -1000 ? joA : jA), foOB = fo_of(H, joB > -1000 ? joB : jB);
 
@@ -688,8 +691,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
         // Loads of step zs + PD's inputs (see the streams above); with a
         // staging function, duty registers are first staged.
         auto prefetch = [&](int zs, bool steady, Real (&vA)[NF][VX], Real (&vB)[NF][VX], Real (&dA2)[NF][VX],
-                            Real (&dB2)[NF][VX], Real (&rA)[NF][VX], Real (&rB)[NF][VX],
-                            auto&& stage_fn) __attribute__((always_inline)) {
+                            Real (&dB2)[NF][VX], Real (&rA)[NF][VX], Real (&rB)[NF][VX], Real (&wA)[NF][VX],
+                            Real (&wB)[NF][VX], auto&& stage_fn) __attribute__((always_inline)) {
             const int f = (int)fresh_s((uint32_t)flags);
             // per-lane offsets, formed here from the uniform parts (fresh
             // copies keep the compiler from hoisting them into registers
@@ -723,6 +726,21 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
             if (f & F_D2_B) { stage_fn(fresh_s(uB2) + lane_b, dB2); fetch(!(f & F_PV_B), kvB, oB, dB2); }
             if (f & F_O_A) { stage_fn(fresh_s(uOA) + lane_b, rA); fetch(f & F_PT, H, oOA, rA); }
             if (f & F_O_B) { stage_fn(fresh_s(uOB) + lane_b, rB); fetch(f & F_PT, H, oOB, rB); }
+            if constexpr (S::LEAPFROG) {
+                // level kf-2 of a computing row: the time level of parity
+                // opposite to kv's, slab zs + PD - RZ*kf
+                uint32_t oU[VX];
+                if (f & F_CMP_A) {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) oU[v] = fresh_s(foUA) + xb[v];
+                    fetch(!(f & F_PV_A), kvA + 1, oU, wA);
+                }
+                if (f & F_CMP_B) {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) oU[v] = fresh_s(foUB) + xb[v];
+                    fetch(!(f & F_PV_B), kvB + 1, oU, wB);
+                }
+            }
         };
 
         Real ring[NS][RING][NF][VX];
@@ -730,6 +748,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
         // kv of a row (its input ring);
         // p2: duty level kv-1; po: the out-of-span row.
         Real qA[PD][NF][VX], qB[PD][NF][VX], p2A[PD][NF][VX], p2B[PD][NF][VX], poA[PD][NF][VX], poB[PD][NF][VX];
+        // second-order-in-time stencils: level kf-2 of each row (the first
+        // computed level's previous time level)
+        Real uA[PD][NF][VX], uB[PD][NF][VX];
         // copied levels (row A / B, input array 0 / 1) of slab zs + PD
         Real cpv[PD][2][2][NF][VX];
 #pragma unroll
@@ -739,6 +760,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
 #pragma unroll
                 for (int c = 0; c < PD; ++c) {
                     qA[c][f][v] = qB[c][f][v] = p2A[c][f][v] = p2B[c][f][v] = poA[c][f][v] = poB[c][f][v] = Real(0);
+                    uA[c][f][v] = uB[c][f][v] = Real(0);
                     cpv[c][0][0][f][v] = cpv[c][0][1][f][v] = cpv[c][1][0][f][v] = cpv[c][1][1][f][v] = Real(0);
                 }
 #pragma unroll
@@ -766,11 +788,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                 lcs[i] = fresh_v(lcs[i]);
                 gos[i] = fresh_v(gos[i]);
             }
-            Real vcA[NF][VX], vcB[NF][VX];
+            Real vcA[NF][VX], vcB[NF][VX], vuA[NF][VX], vuB[NF][VX];
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int v = 0; v < VX; ++v) { vcA[f][v] = qA[ph % PD][f][v]; vcB[f][v] = qB[ph % PD][f][v]; }
+                for (int v = 0; v < VX; ++v) {
+                    vcA[f][v] = qA[ph % PD][f][v];
+                    vcB[f][v] = qB[ph % PD][f][v];
+                    vuA[f][v] = uA[ph % PD][f][v];
+                    vuB[f][v] = uB[ph % PD][f][v];
+                }
             // the readers of this wave's stage rows are done with the buffer
             if constexpr (RLX) wait(1, zs - (KK::DB ? 2 : 1));
             // ---- A: stage every plane the levels read this step ------------------
@@ -821,6 +848,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                 // every plane is inside).  A duty register is staged before its
                 // next load is issued.
                 prefetch(zs, STEADY, qA[ph % PD], qB[ph % PD], p2A[ph % PD], p2B[ph % PD], poA[ph % PD], poB[ph % PD],
+                         uA[ph % PD], uB[ph % PD],
                          [&](uint32_t la, const Real (&src)[NF][VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
                 if constexpr (CPF) {
                     const int q = zs + PD;   // the slab the copy stores at step zs + PD
@@ -926,12 +954,41 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                     }
                 }
                 Real prev[NF][VX];
+                // second-order-in-time stencils: level k-2 at a slot's own cell,
+                // the oldest slab of the ring two slots back, taken from it
+                // before the previous slot's iteration overwrites it
+                Real uold[NF][VX];
                 // x/y neighbours of a slot, read from the stage one slot ahead
                 // of its use (a one-deep software pipeline: deeper prefetching
                 // would hold too many registers)
                 Real nb[LDEP + 1][4 * R][NF][VX];
+                // coefficients of a slot's plane (stencils with coefficient
+                // arrays), loaded with its neighbours, LDEP slots ahead: in the
+                // steady range every slot's offset (0 for unused slots: the
+                // window's first plane, NF*(zs - RZ*L) >= 0) stays inside the
+                // arrays; elsewhere only slots whose plane is inside the grid load
+                Real cfp[LDEP + 1][S::NCOEF > 0 ? S::NCOEF : 1][NF][VX];
                 auto load_nb = [&](auto tc) __attribute__((always_inline)) {
                     constexpr int t = decltype(tc)::value;
+                    if constexpr (S::NCOEF > 0) {
+#pragma unroll
+                        for (int g = 0; g < NF; ++g) {
+                            const bool zvt = ((cm & zS[g]) >> t) & 1u;
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) {
+                                if (STEADY || zvt) {
+                                    const uint32_t go = gos[t] + xb[v];
+#pragma unroll
+                                    for (int m = 0; m < S::NCOEF; ++m)
+                                        cfp[t % (LDEP + 1)][m][g][v] =
+                                            ld_at(at(a.coef.arr[m], e0b + (int64_t)g * plane_b), go);
+                                } else {
+#pragma unroll
+                                    for (int m = 0; m < S::NCOEF; ++m) cfp[t % (LDEP + 1)][m][g][v] = Real(0);
+                                }
+                            }
+                        }
+                    }
                     const uint32_t lb = lcs[t - 1] + BOFF;     // corner of (level - 1, row)
 #pragma unroll
                     for (int g = 0; g < NF; ++g) {
@@ -999,6 +1056,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                                 for (int v = 0; v < VX; ++v) {
                                     Nbhd<Real, R> n;
                                     n.c = ring[s - 1][P(RZ)][g][v];
+                                    if constexpr (S::LEAPFROG) {
+                                        // the first computed level of a row takes
+                                        // level kf-2 from its HBM stream
+                                        if constexpr (s == 1)
+                                            n.uo = vuA[g][v];
+                                        else if constexpr (SBK >= 0)
+                                            n.uo = s == SBK + 1 ? vuB[g][v] : uold[g][v];
+                                        else
+                                            n.uo = s == sb + 1 ? vuB[g][v] : uold[g][v];
+                                    }
 #pragma unroll
                                     for (int r = 1; r <= R; ++r) {
                                         // plane g -/+ r of the slab: slab offset floor((g -/+ r) / NF),
@@ -1017,20 +1084,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                                     }
                                     Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
                                     if constexpr (S::NCOEF > 0) {
-                                        // Coefficients of the slot's plane.  In the steady range
-                                        // every slot's offset (0 for unused slots: the window's
-                                        // first plane, NF*(zs - RZ*L) >= 0) stays inside the
-                                        // arrays; elsewhere only slots whose plane is inside the
-                                        // grid load.
-                                        if (STEADY || zv) {
-                                            const uint32_t go = gos[s] + xb[v];
 #pragma unroll
-                                            for (int m = 0; m < S::NCOEF; ++m)
-                                                cf[m] = ld_at(at(a.coef.arr[m], e0b + (int64_t)g * plane_b), go);
-                                        } else {
-#pragma unroll
-                                            for (int m = 0; m < S::NCOEF; ++m) cf[m] = Real(0);
-                                        }
+                                        for (int m = 0; m < S::NCOEF; ++m) cf[m] = cfp[s % (LDEP + 1)][m][g][v];
                                     }
                                     nv[g][v] = S::apply(n, a.coef.k, cf);
                                 }
@@ -1065,11 +1120,14 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                                 }
                             }
                         }
-                        // slot s-1's ring takes its newest slab
+                        // slot s-1's ring takes its newest slab (its oldest, level
+                        // k-2 of slot s+1, kept first)
 #pragma unroll
                         for (int g = 0; g < NF; ++g) {
 #pragma unroll
                             for (int v = 0; v < VX; ++v) {
+                                if constexpr (S::LEAPFROG) uold[g][v] = UNR == RING ? ring[s - 1][P(0)][g][v]
+                                                                                     : ring[s - 1][0][g][v];
                                 if constexpr (UNR == RING) {
                                     ring[s - 1][P(0)][g][v] = prev[g][v];
                                 } else {
@@ -1148,7 +1206,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
         auto no_stage = [](uint32_t, const Real (&)[NF][VX]) {};
         static_for<0, PD>([&](auto pc) __attribute__((always_inline)) {
             constexpr int c = decltype(pc)::value;
-            prefetch(-RING - PD + c, false, qA[c], qB[c], p2A[c], p2B[c], poA[c], poB[c], no_stage);
+            prefetch(-RING - PD + c, false, qA[c], qB[c], p2A[c], p2B[c], poA[c], poB[c], uA[c], uB[c], no_stage);
         });
         __syncthreads();
         using General = std::integral_constant<bool, false>;

@@ -68,9 +68,7 @@ def test_naive_plane_tiles_bitwise(stencil):
 
 def test_leapfrog_with_initial_velocity_bitwise():
     """The second-order-in-time stencil reads buf1 as u^{-1}: with u^{-1} != u^0
-    both naive variants follow the oracle bit for bit, in FP64 and FP32, and
-    planning it with the blocked algorithm is refused."""
-    import paper_1510_04995_amd.girih as G
+    both naive variants follow the oracle bit for bit, in FP64 and FP32."""
     n = (69, 33, 27)
     u0, c, arr = inputs("25l", *n, seed=7)
     rng = np.random.default_rng(8)
@@ -82,9 +80,76 @@ def test_leapfrog_with_initial_velocity_bitwise():
                   {"variant": 1, "threads_x": 64, "threads_y": 8, "tile_z": 16}):
             got, _ = run_gpu("25l", dtype, u0, c, arr, 5, algo="naive", params=p, prev=prev)
             assert_bitwise(got, ref, "leapfrog %s %s" % (dtype, p))
-    with pytest.raises(G.GirihError) as e:
-        run_gpu("25l", "f64", u0, c, arr, 1, algo="mwd")
-    assert e.value.code == G.E_UNSUPPORTED
+
+
+def leapfrog_prev(u0, seed):
+    """u^{-1}: u^0's halo, a random interior."""
+    rng = np.random.default_rng(seed)
+    prev = u0.copy()
+    prev[4:-4, 4:-4, 4:-4] = rng.random(tuple(d - 8 for d in u0.shape))
+    return prev
+
+
+# Second-order-in-time 25-point stencil, blocked (dtype, Dw, cells per lane,
+# waves along x, N_F, tile_x or 0, grid, list of T): every compiled shape,
+# u^{-1} != u^0, T from one step to several rows, with even and odd numbers
+# of diamond rows (an odd count starts from the plan's own pair, which then
+# receives both input levels)
+MWD_LEAPFROG_CASES = [
+    ("f64", 16, 1, 1, 1, 0, (150, 50, 22), [1, 2, 3, 5, 11]),
+    ("f64", 16, 1, 1, 1, 40, (131, 37, 19), [4, 7]),
+    ("f64", 8, 1, 2, 1, 0, (140, 30, 20), [1, 2, 3, 6]),
+    ("f32", 16, 1, 1, 1, 0, (100, 45, 21), [2, 3, 7]),
+    ("f32", 16, 1, 1, 2, 0, (100, 45, 21), [1, 4, 9]),
+    ("f32", 16, 1, 1, 2, 0, (70, 20, 8), [3, 6]),
+    ("f32", 8, 1, 2, 1, 0, (140, 30, 20), [3, 5]),
+]
+
+
+@pytest.mark.parametrize("dtype,dw,vx,wx,nf,tx,n,Ts", MWD_LEAPFROG_CASES)
+def test_mwd_leapfrog_bitwise(dtype, dw, vx, wx, nf, tx, n, Ts):
+    u0, c, arr = inputs("25l", *n, seed=9)
+    prev = leapfrog_prev(u0, 10)
+    params = mwd_params(dw, vx, wx, tx, nf)
+    for T in Ts:
+        print("mwd leapfrog", dtype, dw, vx, wx, nf, tx, n, T, flush=True)
+        got, info = run_gpu("25l", dtype, u0, c, arr, T, algo="mwd", params=params, prev=prev)
+        q = info["params"]
+        assert (q["diamond_width"], q["wavefront_depth"]) == (dw, nf)
+        assert_bitwise(got, oracle_run("25l", u0, c, arr, T, dtype, prev=prev),
+                       "mwd leapfrog %s Dw=%d nf=%d T=%d" % (dtype, dw, nf, T))
+        naive, _ = run_gpu("25l", dtype, u0, c, arr, T, algo="naive", prev=prev)
+        assert_bitwise(got, naive, "mwd leapfrog vs naive")
+
+
+def test_mwd_leapfrog_schedules_halo_and_thin_grids():
+    """The blocked second-order stencil with the dependency-driven schedule,
+    a nonzero halo (the general-halo instance), and grids thinner than a
+    diamond or a slab."""
+    params = mwd_params(16, 1, 1)
+    u0, c, arr = inputs("25l", 120, 44, 23, seed=11)
+    prev = leapfrog_prev(u0, 12)
+    for T in (1, 4, 9):
+        print("mwd leapfrog sweep", T, flush=True)
+        got, _ = run_gpu("25l", "f64", u0, c, arr, T, algo="mwd", params=dict(params, variant=1), prev=prev,
+                         check=True)
+        assert_bitwise(got, oracle_run("25l", u0, c, arr, T, "f64", prev=prev), "leapfrog sweep T=%d" % T)
+    u0, c, arr = inputs("25l", 60, 30, 14, seed=13)
+    rng = np.random.default_rng(13)
+    halo = np.ones(u0.shape, bool)
+    halo[4:-4, 4:-4, 4:-4] = False
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    prev = leapfrog_prev(u0, 14)
+    for dtype, nf in (("f64", 1), ("f32", 2)):
+        print("mwd leapfrog nonzero halo", dtype, flush=True)
+        got, _ = run_gpu("25l", dtype, u0, c, arr, 5, algo="mwd", params=mwd_params(16, 1, 1, 0, nf), prev=prev)
+        assert_bitwise(got, oracle_run("25l", u0, c, arr, 5, dtype, prev=prev), "leapfrog nonzero halo %s" % dtype)
+    for n in ((9, 5, 3), (1, 1, 1), (33, 7, 2)):
+        u0, c, arr = inputs("25l", *n, seed=15)
+        prev = leapfrog_prev(u0, 16)
+        print("mwd leapfrog thin", n, flush=True)
+        got, _ = run_gpu("25l", "f64", u0, c, arr, 6, algo="mwd", prev=prev)
+        assert_bitwise(got, oracle_run("25l", u0, c, arr, 6, "f64", prev=prev), "leapfrog thin %s" % (n,))
 
 
 # (stencil, dtype, Dw, cells per lane, waves along x, tile_x or 0, grid (nx, ny, nz), list of T):
@@ -471,7 +536,7 @@ def test_mwd_odd_size_twin(stencil, dtype, n, T):
 
 @pytest.mark.parametrize("name,dtype", [("25pt-const-512", "f64"), ("25pt-var-384", "f64"), ("25pt-var-384", "f32"),
                                         ("7pt-var-256x512x1024", "f64"), ("7pt-var-256x512x1024", "f32"),
-                                        ("25pt-leapfrog-512", "f64")])
+                                        ("25pt-leapfrog-512", "f64"), ("25pt-leapfrog-512", "f32")])
 def test_full_size_workloads(name, dtype):
     """The other workloads at their full sizes in their default launch
     configurations: the blocked sweep (where one exists) and the naive sweep
@@ -487,7 +552,7 @@ def test_full_size_workloads(name, dtype):
     g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
     coefs = [] if arr is None else [torch.from_numpy(a.astype(npdt)).to(dev) for a in arr]
     consts = None if c is None else [float(x) for x in c]
-    algos = ("mwd", "naive") if w.stencil != "25l" else ("naive",)
+    algos = ("mwd", "naive")
     res = {}
     for algo in algos:
         print("full size", name, dtype, algo, flush=True)

@@ -92,9 +92,8 @@ def test_plan_rejects_bad_tile_params():
 
 
 def test_mwd_variable_coefficient_shapes():
-    """Blocked plans of the variable-coefficient stencils exist for the
-    registered (spill-free) shapes only; the second-order-in-time stencil has
-    none."""
+    """Blocked plans of the variable-coefficient and the second-order-in-time
+    stencils exist for the registered (spill-free) shapes only."""
     for st, h, dt, dw in (("7v", 1, "f64", 8), ("7v", 1, "f32", 8), ("25v", 4, "f64", 8), ("25v", 4, "f32", 16)):
         p = G.girih_plan(st, dt, grid(h=h), None, "mwd")
         assert G.girih_plan_info(p)[0]["diamond_width"] == dw
@@ -102,8 +101,12 @@ def test_mwd_variable_coefficient_shapes():
     with pytest.raises(G.GirihError) as e:
         G.girih_plan("7v", "f64", grid(), None, "mwd", {"diamond_width": 12})     # spills: not compiled
     assert e.value.code == G.E_UNSUPPORTED
+    for dt in ("f64", "f32"):
+        p = G.girih_plan("25l", dt, grid(h=4), (0.1, 0.1, 0.1, 0.1, 0.1), "mwd")
+        assert G.girih_plan_info(p)[0]["diamond_width"] == 16
+        G.girih_destroy(p)
     with pytest.raises(G.GirihError) as e:
-        G.girih_plan("25l", "f64", grid(h=4), (0.1, 0.1, 0.1, 0.1, 0.1), "mwd")
+        G.girih_plan("25l", "f64", grid(h=4), (0.1, 0.1, 0.1, 0.1, 0.1), "mwd", {"diamond_width": 24})
     assert e.value.code == G.E_UNSUPPORTED
 
 
@@ -139,23 +142,27 @@ def test_candidates_cover_compiled_variants():
 
 def test_leapfrog_plans():
     """The second-order-in-time 25-point stencil: naive plans stream four
-    domain-sized arrays (V, U read and written, C); no blocked kernel."""
+    domain-sized arrays (V, U read and written, C); blocked plans default to
+    Dw = 16, whose B_C with N_D = 3 (the two time levels and C) is
+    2*8*4*[(32 - 8) + (48 + 8)]/256 = 20 B per update in FP64."""
     g = G.make_grid(64, 48, 40, 4)
     c = (-205.0 / 24.0, 1.6, -0.2, 8.0 / 315.0, -1.0 / 560.0)
     p = G.girih_plan("25l", "f64", g, c, "naive")
     _, _, bytes_per_lup = G.girih_plan_info(p)
     assert bytes_per_lup == 32.0
     G.girih_destroy(p)
-    with pytest.raises(G.GirihError) as e:
-        G.girih_plan("25l", "f64", g, c, "mwd")
-    assert e.value.code == G.E_UNSUPPORTED
+    p = G.girih_plan("25l", "f64", g, c, "mwd")
+    q, _, bytes_per_lup = G.girih_plan_info(p)
+    assert q["diamond_width"] == 16 and bytes_per_lup == pytest.approx(20.0)
+    assert {(x["diamond_width"], x["wavefront_depth"]) for x in G.girih_candidates(p)} == {(16, 1), (8, 1)}
+    G.girih_destroy(p)
     with pytest.raises(G.GirihError) as e:
         G.girih_plan("25l", "f64", g, None, "naive")          # constants are required
     assert e.value.code == G.E_INVALID
 
 
 @pytest.mark.parametrize("stencil,dtype", [("7c", "f64"), ("7c", "f32"), ("25c", "f64"), ("7v", "f64"), ("7v", "f32"),
-                                           ("25v", "f64"), ("25v", "f32")])
+                                           ("25v", "f64"), ("25v", "f32"), ("25l", "f64"), ("25l", "f32")])
 def test_plan_info_reports_the_papers_code_balance(stencil, dtype):
     """girih_plan_info gives the paper's B_C (Section "Memory traffic model")
     of the plan's diamond width, scaled to the element size, with N_D the
@@ -163,8 +170,8 @@ def test_plan_info_reports_the_papers_code_balance(stencil, dtype):
     a default blocked plan."""
     from oracle import models
     R = 1 if stencil.startswith("7") else 4
-    nd = 2 + {"7c": 0, "7v": 7, "25c": 0, "25v": 13}[stencil]
-    cc = {"7c": (0.4, 0.1), "25c": (0.2, 0.05, 0.04, 0.03, 0.0133)}.get(stencil)
+    nd = 2 + {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1}[stencil]
+    cc = {"7c": (0.4, 0.1), "25c": (0.2, 0.05, 0.04, 0.03, 0.0133), "25l": (-8.5, 1.6, -0.2, 0.025, -0.002)}.get(stencil)
     p = G.girih_plan(stencil, dtype, G.make_grid(96, 80, 40, R), cc, "mwd")
     params, lds, bpl = G.girih_plan_info(p)
     G.girih_destroy(p)
