@@ -30,6 +30,12 @@
  *        value the point holds in the array being overwritten, i.e. time
  *        level t-1; buf1 therefore holds u^{-1} on entry, not a copy of the
  *        halo only.  One coefficient array C and five constants.
+ *   27b (the 27-point box stencil of Section "Handling other stencil types",
+ *        constant coefficients by distance class; the paper prints no
+ *        listing for it, so the order is this file's):
+ *        ((c0*V + c1*F) + c2*E) + c3*K, where F, E and K sum the 6 face, 12
+ *        edge and 8 corner neighbours, each in lexicographic order of the
+ *        offset (dk, dj, di), components -1 < 0 < +1, dk slowest.
  *
  * Array layout (Listings 1-4 index U[k][j][i], i fastest): element (k,j,i),
  * with k in [-h, nz+h), j in [-h, ny+h), i in [-h, nx+h), lives at
@@ -44,6 +50,7 @@
 #define ST_25C 2
 #define ST_25V 3
 #define ST_25L 4
+#define ST_27B 5
 
 #define IDX(k, j, i) ((((int64_t)(k) + h) * pitch_y + ((int64_t)(j) + h)) * pitch_x + ((int64_t)(i) + h))
 
@@ -82,6 +89,19 @@ static void step_##SUFFIX(int stencil, int64_t nx, int64_t ny, int64_t nz, int64
                                + V[IDX(k + r, j, i)] + V[IDX(k - r, j, i)];              \
                         u = u + c[r] * s;                                                \
                     }                                                                    \
+                } else if (stencil == ST_27B) {                                          \
+                    REAL f = 0, e = 0, q = 0;                                            \
+                    int nf = 0, ne = 0, nq = 0;                                          \
+                    for (int dk = -1; dk <= 1; dk++)                                     \
+                        for (int dj = -1; dj <= 1; dj++)                                 \
+                            for (int di = -1; di <= 1; di++) {                           \
+                                const int m = (dk != 0) + (dj != 0) + (di != 0);         \
+                                const REAL v = V[IDX(k + dk, j + dj, i + di)];           \
+                                if (m == 1) { f = nf++ ? f + v : v; }                    \
+                                else if (m == 2) { e = ne++ ? e + v : v; }               \
+                                else if (m == 3) { q = nq++ ? q + v : v; }               \
+                            }                                                            \
+                    u = c[0] * V[p] + c[1] * f + c[2] * e + c[3] * q;                    \
                 } else if (stencil == ST_25L) {                                          \
                     REAL b = c[0] * V[p];                                                \
                     for (int r = 1; r <= 4; r++) {                                       \
@@ -110,8 +130,8 @@ int oracle_sweep_##SUFFIX(int stencil, int64_t nx, int64_t ny, int64_t nz, int64
                           const REAL *const_coefs, const REAL *const *coef_arrays,       \
                           int64_t T)                                                     \
 {                                                                                        \
-    const int64_t R = (stencil == ST_7C || stencil == ST_7V) ? 1 : 4;                    \
-    if (stencil < 0 || stencil > 4) return -1;                                           \
+    const int64_t R = (stencil == ST_7C || stencil == ST_7V || stencil == ST_27B) ? 1 : 4; \
+    if (stencil < 0 || stencil > 5) return -1;                                           \
     if (nx < 0 || ny < 0 || nz < 0 || T < 0 || h != R) return -1;                        \
     if (pitch_x < nx + 2 * h || pitch_y < ny + 2 * h) return -1;                         \
     REAL *V = buf0, *U = buf1;                                                           \

@@ -21,10 +21,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-STENCILS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3, "25l": 4}
-RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4}
-N_COEF_ARRAYS = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1}
-N_CONST_COEFS = {"7c": 2, "7v": 0, "25c": 5, "25v": 0, "25l": 5}
+STENCILS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3, "25l": 4, "27b": 5}
+RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4, "27b": 1}
+N_COEF_ARRAYS = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1, "27b": 0}
+N_CONST_COEFS = {"7c": 2, "7v": 0, "25c": 5, "25v": 0, "25l": 5, "27b": 4}
 
 _lib = None
 
@@ -73,8 +73,8 @@ def sweep(stencil, buf0, buf1, T, const_coefs=None, coef_arrays=None):
     ``buf0``/``buf1``: C-contiguous float64 or float32 arrays of shape
     ``(nz+2h, ny+2h, nx+2h)`` (no padding; h is the stencil radius).  ``buf0`` holds u^0 with
     its halo; ``buf1`` must carry the same halo (for the second-order-in-time
-    ``25l`` its interior is u^{-1}).  ``const_coefs``: c0,c1 (7c) or c0..c4
-    (25c, 25l).  ``coef_arrays``: 7 (7v), 13 (25v) or 1 (25l) arrays in the
+    ``25l`` its interior is u^{-1}).  ``const_coefs``: c0,c1 (7c), c0..c4
+    (25c, 25l) or c0..c3 (27b).  ``coef_arrays``: 7 (7v), 13 (25v) or 1 (25l) arrays in the
     same layout as the field.
     """
     lib = _load()

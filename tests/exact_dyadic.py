@@ -37,6 +37,12 @@ def term_table(stencil):
             x, y, z = _axis(r)
             t += [(3 * r - 2, x), (3 * r - 1, y), (3 * r, z)]
         return t
+    if stencil == "27b":
+        # the 26 neighbours of the 3x3x3 box, weight by how many of the three
+        # offsets are nonzero (faces 1, edges 2, corners 3)
+        import itertools
+        offs = [d for d in itertools.product((-1, 0, 1), repeat=3) if d != (0, 0, 0)]
+        return [(0, c)] + [(m, [d for d in offs if sum(1 for a in d if a) == m]) for m in (1, 2, 3)]
     raise ValueError(stencil)
 
 
@@ -59,7 +65,7 @@ def exact_sweep(stencil, u0, T, consts=None, arrays=None):
     ``u0`` is (nz+2h, ny+2h, nx+2h) float64 with its fixed halo; ``consts`` or
     ``arrays`` as for the oracle.
     """
-    h = 1 if stencil in ("7c", "7v") else 4
+    h = 1 if stencil in ("7c", "7v", "27b") else 4
     table = term_table(stencil)
     N, E = _to_dyadic(u0)
     if arrays is not None:

@@ -24,17 +24,20 @@ paper does not give its initial data; the recipe used here is:
   constants: the eighth-order central second-difference weights
   c1..c4 = 8/5, -1/5, 8/315, -1/560 and c0 = -6*(c1+c2+c3+c4), so that the
   bracket is a discrete Laplacian; both buffers start as u^0 (zero initial
-  velocity).
+  velocity);
+* the 27-point box stencil ("27b", constant weights by distance class:
+  centre, 6 faces, 12 edges, 8 corners) takes the field, then c0..c3 drawn
+  and normalised so that c0 + 6*c1 + 12*c2 + 8*c3 = 1.
 """
 import math
 from dataclasses import dataclass, field as dc_field
 
 import numpy as np
 
-STENCILS = ("7c", "7v", "25c", "25v", "25l")
-RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4}
-N_COEF_ARRAYS = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1}
-N_CONST_COEFS = {"7c": 2, "7v": 0, "25c": 5, "25v": 0, "25l": 5}
+STENCILS = ("7c", "7v", "25c", "25v", "25l", "27b")
+RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4, "27b": 1}
+N_COEF_ARRAYS = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1, "27b": 0}
+N_CONST_COEFS = {"7c": 2, "7v": 0, "25c": 5, "25v": 0, "25l": 5, "27b": 4}
 
 
 def laplacian8_weights():
@@ -64,8 +67,8 @@ class Workload:
         return self.nx * self.ny * self.nz * self.T
 
 
-# The workloads of this study: the five of its configurations and the
-# second-order 25-point stencil.  Sizes are interior points (x fastest).
+# The workloads of this study: the five of its configurations, the
+# second-order 25-point stencil and the 27-point box stencil.  Sizes are interior points (x fastest).
 WORKLOADS = {
     "7pt-const-64": Workload("7pt-const-64", "7c", 64, 64, 64, 16, (0.4, 0.1),
                              note="naive GPU sweep vs oracle; fits in cache"),
@@ -79,6 +82,8 @@ WORKLOADS = {
                                      note="7 per-point coefficient arrays; unseen by the tuner's training"),
     "25pt-leapfrog-512": Workload("25pt-leapfrog-512", "25l", 512, 512, 512, 32, None, ("f64", "f32"),
                                   note="Listing 3 as printed: second order in time, one per-point array"),
+    "27pt-box-512": Workload("27pt-box-512", "27b", 512, 512, 512, 32, None, ("f64", "f32"),
+                             note="27-point box, c0..c3 by distance class, drawn and normalised"),
 }
 
 
@@ -135,6 +140,13 @@ def field_and_coefs(stencil, nx, ny, nz, seed=0, const_coefs=None, dtype="f64"):
         else:
             c = rng.random(5)
             s = math.fsum([c[0]] + [c[r] for r in range(1, 5) for _ in range(6)])
+            consts = c / s
+    elif stencil == "27b":
+        if const_coefs is not None:
+            consts = np.array(const_coefs, dtype=np.float64)
+        else:
+            c = rng.random(4)
+            s = math.fsum([c[0]] + [c[1]] * 6 + [c[2]] * 12 + [c[3]] * 8)
             consts = c / s
     elif stencil == "25l":
         consts = laplacian8_weights() if const_coefs is None else np.array(const_coefs, dtype=np.float64)
