@@ -27,7 +27,8 @@ Beside the headline value the line carries:
                 the FP64 result, measured outside the timed region;
   per_stencil   every other workload of the study (25-point constant 512^3,
                 25-point variable 384^3, 7-point variable 256x512x1024, the
-                second-order 25-point stencil on 512^3), blocked
+                second-order 25-point stencil on 512^3; the 27-point box
+                stencil on 512^3, naive only), blocked
                 and naive, FP64 and FP32, timed the same way outside the timed
                 region, with the FP32 error against the FP64 blocked result
                 (which equals the FP64 oracle bit for bit, as the GPU parity
@@ -49,7 +50,8 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 WORKLOAD = "7pt-const-512"
 STENCIL_NAMES = {"7c": "7-point constant (c0=0.4, c1=0.1)", "25c": "25-point constant (c0..c4 drawn, normalised)",
                  "7v": "7-point variable (7 coefficient arrays)", "25v": "25-point variable (13 coefficient arrays)",
-                 "25l": "25-point second order in time (c0..c4, C array)"}
+                 "25l": "25-point second order in time (c0..c4, C array)",
+                 "27b": "27-point box (c0..c3 by distance class)"}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "mwd_7pt_const_512_f64_traffic.txt")
 KERNEL_SOURCES = ("paper_1510_04995_amd/csrc/mwd.hpp", "paper_1510_04995_amd/csrc/stencils.hpp",
                   "paper_1510_04995_amd/csrc/kernels_7c_f64.hip", "paper_1510_04995_amd/csrc/instantiate.hpp")
@@ -161,9 +163,11 @@ def per_stencil(torch, dev, reps=3):
     import paper_1510_04995_amd as P
     from workloads import WORKLOADS, field_and_coefs
     res = {}
-    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512"):
+    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512", "27pt-box-512"):
         w = WORKLOADS[name]
         h = w.radius
+        # (the box stencil has the naive sweep only)
+        algos = ("naive",) if w.stencil == "27b" else ("mwd", "naive")
         log("inputs " + name)
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0)
         consts = None if c is None else [float(x) for x in c]
@@ -173,7 +177,7 @@ def per_stencil(torch, dev, reps=3):
             npdt = np.float64 if dtype == "f64" else np.float32
             g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
             coefs = [] if arr is None else [torch.from_numpy(a.astype(npdt)).to(dev) for a in arr]
-            for algo in ("mwd", "naive"):
+            for algo in algos:
                 log("time %s %s %s" % (name, dtype, algo))
                 sw = P.Sweep(w.stencil, dtype, w.nx, w.ny, w.nz, consts, algo)
                 info = sw.info()
@@ -195,11 +199,18 @@ def per_stencil(torch, dev, reps=3):
                     ref = ref64 if dtype == "f64" else None
                     if ref is not None:
                         entry["mwd_vs_naive_f64_bitwise_diff"] = P.error_norms(out, ref, h, w.nx, w.ny, w.nz)[2]
+                    elif dtype == "f64":
+                        ref64 = out.clone()
+                    elif "mwd" not in algos:
+                        rel, mx, _ = P.error_norms(out, ref64, h, w.nx, w.ny, w.nz)
+                        entry["f32_rel_l2_vs_f64"] = float("%.3e" % rel)
+                        entry["f32_max_abs_vs_f64"] = float("%.3e" % mx)
                 sw.close()
                 del out
             del g0, coefs
             torch.cuda.empty_cache()
-        entry["mwd_vs_naive_f64"] = round(entry["mwd_f64_glups"] / entry["naive_f64_glups"], 3)
+        if "mwd" in algos:
+            entry["mwd_vs_naive_f64"] = round(entry["mwd_f64_glups"] / entry["naive_f64_glups"], 3)
         del ref64
         torch.cuda.empty_cache()
         res[name] = entry
@@ -210,7 +221,7 @@ def oracle_rates(O, seconds=4.0):
     """The oracle on the other workloads: a few steps each on all threads."""
     from workloads import WORKLOADS, field_and_coefs
     out = {}
-    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512"):
+    for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512", "27pt-box-512"):
         w = WORKLOADS[name]
         log("oracle " + name)
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0)

@@ -52,10 +52,16 @@ typedef enum {
     GIRIH_7PT_VAR = 1,    /* 7 coefficient arrays C0..C6            */
     GIRIH_25PT_CONST = 2, /* c0..c4 scalars, radius 4               */
     GIRIH_25PT_VAR = 3,   /* 13 coefficient arrays C00..C12, R = 4  */
-    GIRIH_25PT_LEAPFROG = 4 /* c0..c4 scalars and 1 array C, R = 4:
+    GIRIH_25PT_LEAPFROG = 4, /* c0..c4 scalars and 1 array C, R = 4:
                              * u^{t+1} = (2u^t - u^{t-1}) + C*(bracket of u^t);
                              * buf1 holds u^{t-1} = u^{-1} on entry (its
                              * interior is read), buf0 holds u^0 */
+    GIRIH_27PT_BOX = 5      /* c0..c3 scalars, R = 1: the 27-point box stencil
+                             * (Section "Handling other stencil types"),
+                             * ((c0*V + c1*F) + c2*E) + c3*K with F, E, K the
+                             * sums of the 6 face, 12 edge and 8 corner
+                             * neighbours, each in lexicographic order of the
+                             * offset (dz, dy, dx); naive sweep only */
 } girih_stencil;
 
 typedef enum { GIRIH_F64 = 0, GIRIH_F32 = 1 } girih_dtype;
@@ -64,10 +70,11 @@ typedef enum {
     GIRIH_NAIVE = 0, /* T launches of one full-domain Jacobi step              */
     GIRIH_MWD = 1    /* diamond rows: one launch per row of diamond tiles      */
 } girih_algo;
-/* GIRIH_MWD exists for every stencil, in the diamond shapes compiled for it
- * (girih_candidates); girih_plan returns GIRIH_E_UNSUPPORTED for a shape
- * that was not compiled.  For the second-order-in-time stencil a level also
- * reads the level two below it at its own cell. */
+/* GIRIH_MWD exists for the five star stencils, in the diamond shapes
+ * compiled for them (girih_candidates); girih_plan returns
+ * GIRIH_E_UNSUPPORTED for a shape that was not compiled, and for
+ * GIRIH_27PT_BOX.  For the second-order-in-time stencil a level also reads
+ * the level two below it at its own cell. */
 
 /* Grid descriptor, in elements. */
 typedef struct girih_grid {

@@ -72,6 +72,19 @@ void add_naive_tile(std::vector<KernelEntry>& t, int st, int dt) {
                             &launch_naive_tile<S, Real, BY>});
 }
 
+template <typename Real>
+hipError_t launch_naive_box(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
+    hipLaunchKernelGGL((naive_box_kernel<Real>), grid, block, 0, stream, *static_cast<const NaiveArgs<Real>*>(args));
+    return hipGetLastError();
+}
+
+// The 27-point box stencil: the cached naive sweep (variant 0).
+template <typename Real>
+void add_box_family(std::vector<KernelEntry>& t, int st, int dt) {
+    t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0, 0,
+                            reinterpret_cast<const void*>(&naive_box_kernel<Real>), &launch_naive_box<Real>});
+}
+
 template <class S, typename Real>
 void add_naive(std::vector<KernelEntry>& t, int st, int dt) {
     t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0, 0,

@@ -1,5 +1,4 @@
-// Kernels of the second-order-in-time 25-point stencil in double precision
-// (naive sweeps only; see instantiate.hpp).
+// Kernels of the second-order-in-time 25-point stencil in double precision.
 #include "instantiate.hpp"
 
 namespace girih {

@@ -68,6 +68,52 @@ naive_step_kernel(NaiveArgs<Real> a) {
     }
 }
 
+// The 27-point box stencil: the same march along z, each lane keeping the
+// 3x3 columns around its own for the planes z-1, z, z+1 in registers (nine
+// loads per plane, the eight beside its own column shared with neighbouring
+// lanes and rows through the caches).
+template <typename Real>
+__global__ void __launch_bounds__(256)
+naive_box_kernel(NaiveArgs<Real> a) {
+    const GridDesc& g = a.g;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t y = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= g.nx || y >= g.ny) return;
+    const int64_t z0 = (int64_t)blockIdx.z * a.z_chunk;
+    int64_t z1 = z0 + a.z_chunk;
+    if (z1 > g.nz) z1 = g.nz;
+    if (z0 >= z1) return;
+    const int64_t plane = g.plane();
+    const int64_t px = g.pitch_x;
+    const Real* __restrict__ V = a.V;
+    Real* __restrict__ U = a.U;
+    // w[d][c]: plane z-1+d, column c = (dy+1)*3 + (dx+1)
+    Real w[3][9];
+    int64_t p = g.idx(z0, y, x);
+    auto load_plane = [&](Real (&dst)[9], int64_t q) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) dst[(dy + 1) * 3 + dx + 1] = V[q + dy * px + dx];
+    };
+    load_plane(w[0], p - plane);
+    load_plane(w[1], p);
+    for (int64_t z = z0; z < z1; ++z, p += plane) {
+        load_plane(w[2], p + plane);
+        Box27<Real> b;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) b.v[d * 9 + c] = w[d][c];
+        U[p] = Stencil27B::apply_box(b, a.coef.k);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            w[0][c] = w[1][c];
+            w[1][c] = w[2][c];
+        }
+    }
+}
+
 // Variant 1: the same sweep with the x/y neighbours of each plane taken from
 // an LDS tile.  A block of 64 x BY threads marches z as above; at every plane
 // it stages the (BY + 2R) x (64 + 2R) tile of V around its columns: each

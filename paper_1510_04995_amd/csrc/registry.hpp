@@ -7,7 +7,7 @@
 
 namespace girih {
 
-enum StencilId { ST_7C = 0, ST_7V = 1, ST_25C = 2, ST_25V = 3, ST_25L = 4 };
+enum StencilId { ST_7C = 0, ST_7V = 1, ST_25C = 2, ST_25V = 3, ST_25L = 4, ST_27B = 5 };
 enum DtypeId { DT_F64 = 0, DT_F32 = 1 };
 enum AlgoId { AL_NAIVE = 0, AL_MWD = 1 };
 
@@ -47,6 +47,8 @@ void register_kernels_25v_f64(std::vector<KernelEntry>&);
 void register_kernels_25v_f32(std::vector<KernelEntry>&);
 void register_kernels_25l_f64(std::vector<KernelEntry>&);
 void register_kernels_25l_f32(std::vector<KernelEntry>&);
+void register_kernels_27b_f64(std::vector<KernelEntry>&);
+void register_kernels_27b_f32(std::vector<KernelEntry>&);
 
 const std::vector<KernelEntry>& kernel_table();
 

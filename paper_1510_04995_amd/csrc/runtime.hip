@@ -51,6 +51,8 @@ const std::vector<KernelEntry>& kernel_table() {
         register_kernels_25v_f32(t);
         register_kernels_25l_f64(t);
         register_kernels_25l_f32(t);
+        register_kernels_27b_f64(t);
+        register_kernels_27b_f32(t);
         return t;
     }();
     return table;
@@ -60,13 +62,14 @@ const std::vector<KernelEntry>& kernel_table() {
 
 namespace {
 
-constexpr int kRadius[5] = {1, 1, 4, 4, 4};
-constexpr int kNCoef[5] = {0, 7, 0, 13, 1};
-constexpr int kNConst[5] = {2, 0, 5, 0, 5};
+constexpr int kNStencils = 6;
+constexpr int kRadius[kNStencils] = {1, 1, 4, 4, 4, 1};
+constexpr int kNCoef[kNStencils] = {0, 7, 0, 13, 1, 0};
+constexpr int kNConst[kNStencils] = {2, 0, 5, 0, 5, 4};
 // domain-sized arrays a naive step streams: V and U, the coefficient arrays,
 // and for the second-order-in-time stencil U's old value read before it is
 // overwritten (U is read and written)
-constexpr int kStreams[5] = {2, 9, 2, 15, 4};
+constexpr int kStreams[kNStencils] = {2, 9, 2, 15, 4, 2};
 
 struct Tuning {
     std::vector<girih_params> model_cands;
@@ -276,7 +279,8 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         // at least two blocks per CU on small grids.
         const bool dflt = !in || (in->threads_x == 0 && in->threads_y == 0 && in->variant == 0);
         if (dflt) {
-            const bool cached = p->stencil == GIRIH_7PT_CONST && p->dtype == GIRIH_F32;
+            // (the box stencil has the cached variant only)
+            const bool cached = (p->stencil == GIRIH_7PT_CONST && p->dtype == GIRIH_F32) || p->stencil == GIRIH_27PT_BOX;
             q.threads_x = 64;
             q.threads_y = cached ? 4 : 16;
             q.variant = cached ? 0 : 1;
@@ -977,7 +981,7 @@ int girih_plan(girih_plan_t* out, girih_stencil stencil, girih_dtype dtype, cons
                const double* const_coefs, girih_algo algo, const girih_params* params) {
     if (!out) return GIRIH_E_INVALID;
     *out = nullptr;
-    if ((int)stencil < 0 || (int)stencil > 4 || (dtype != GIRIH_F64 && dtype != GIRIH_F32) ||
+    if ((int)stencil < 0 || (int)stencil >= kNStencils || (dtype != GIRIH_F64 && dtype != GIRIH_F32) ||
         (algo != GIRIH_NAIVE && algo != GIRIH_MWD))
         return GIRIH_E_INVALID;
     girih_grid g;

@@ -17,6 +17,11 @@
 //   Stencil25L (Listing 3 as printed, second order in time):
 //              (2*V - Uold) + C*(c0*V + c1*S1 + c2*S2 + c3*S3 + c4*S4),
 //              Uold = the point's value at time t-1 (the array being written)
+//   Stencil27B (the 27-point box stencil of Section "Handling other stencil
+//              types"; the paper gives no listing, so the order is the
+//              library's): ((c0*V + c1*F) + c2*E) + c3*K, F / E / K the sums of
+//              the 6 face, 12 edge and 8 corner neighbours, each in
+//              lexicographic order of the offset (dz, dy, dx), -1 < 0 < +1
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -110,6 +115,35 @@ struct Stencil25L {
             b = b + k[r + 1] * s;
         }
         return (Real(2) * n.c - n.uo) + C[0] * b;
+    }
+};
+
+// The 3x3x3 neighbourhood of a point, v[(dz+1)*9 + (dy+1)*3 + (dx+1)].
+template <typename Real>
+struct Box27 {
+    Real v[27];
+};
+
+struct Stencil27B {
+    static constexpr int R = 1, NCOEF = 0, NCONST = 4;
+    static constexpr bool LEAPFROG = false;
+    template <typename Real>
+    __device__ __forceinline__ static Real apply_box(const Box27<Real>& b, const Real* k) {
+        // class of offset m: number of nonzero components (compile-time)
+        Real f = b.v[4], e = b.v[1], q = b.v[0];   // first face (-1,0,0), edge (-1,-1,0), corner (-1,-1,-1)
+#pragma unroll
+        for (int m = 2; m < 27; ++m) {
+            const int cls = (m / 9 != 1) + ((m / 3) % 3 != 1) + (m % 3 != 1);
+            if (m == 4) continue;
+            if (cls == 1) f = f + b.v[m];
+            else if (cls == 2 && m != 1) e = e + b.v[m];
+        }
+#pragma unroll
+        for (int m = 1; m < 27; ++m) {
+            const int cls = (m / 9 != 1) + ((m / 3) % 3 != 1) + (m % 3 != 1);
+            if (cls == 3) q = q + b.v[m];
+        }
+        return ((k[0] * b.v[13] + k[1] * f) + k[2] * e) + k[3] * q;
     }
 };
 

@@ -14,12 +14,12 @@ LIB_PATH = os.path.join(HERE, "libgirih.so")
 OK = 0
 E_INVALID, E_UNSUPPORTED, E_LDS, E_HIP, E_NOMEM, E_NOGPU, E_SCRATCH, E_STALL = -1, -2, -3, -4, -5, -6, -7, -8
 
-STENCIL_IDS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3, "25l": 4}
+STENCIL_IDS = {"7c": 0, "7v": 1, "25c": 2, "25v": 3, "25l": 4, "27b": 5}
 DTYPE_IDS = {"f64": 0, "f32": 1}
 ALGO_IDS = {"naive": 0, "mwd": 1}
 TUNE_MODES = {"exhaustive": 0, "hillclimb": 1, "model": 2}
-RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4}
-N_COEF = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1}
+RADIUS = {"7c": 1, "7v": 1, "25c": 4, "25v": 4, "25l": 4, "27b": 1}
+N_COEF = {"7c": 0, "7v": 7, "25c": 0, "25v": 13, "25l": 1, "27b": 0}
 
 
 class GirihGrid(ctypes.Structure):

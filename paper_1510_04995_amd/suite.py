@@ -25,7 +25,7 @@ import sys
 import time
 
 HBM_PEAK_BYTES = 8.0e12
-STREAMS = {"7c": 2, "7v": 9, "25c": 2, "25v": 15, "25l": 4}
+STREAMS = {"7c": 2, "7v": 9, "25c": 2, "25v": 15, "25l": 4, "27b": 2}
 
 
 def _grid(a, torch, dev):

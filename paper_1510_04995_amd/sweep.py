@@ -18,7 +18,7 @@ def _dtype_name(t):
 
 
 class Sweep:
-    """A plan for ``T`` steps of one stencil ("7c", "7v", "25c", "25v", "25l") on one grid.
+    """A plan for ``T`` steps of one stencil ("7c", "7v", "25c", "25v", "25l", "27b") on one grid.
 
     ``algo``: "mwd" (diamond rows, wavefront along z; "7c" and "25c") or "naive".
     ``params``: dict of ``girih_params`` fields (zeros take defaults).

@@ -27,7 +27,7 @@ def assert_bitwise(a, b, what):
 
 
 CASES_NAIVE = [("7c", (37, 29, 23), 5), ("7v", (35, 19, 21), 4), ("25c", (45, 37, 29), 3), ("25v", (41, 35, 33), 2),
-               ("25l", (43, 37, 31), 3)]
+               ("25l", (43, 37, 31), 3), ("27b", (37, 29, 23), 5), ("27b", (130, 7, 66), 3), ("27b", (1, 1, 1), 2)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -47,6 +47,27 @@ def test_naive_block_shapes():
               {"threads_x": 256, "threads_y": 1, "tile_z": 16}):
         got, _ = run_gpu("7c", "f64", u0, c, arr, 3, algo="naive", params=p)
         assert_bitwise(got, ref, "naive %s" % p)
+
+
+def test_box_block_shapes_halo_and_pitch():
+    """The 27-point box stencil's naive sweep: several block shapes and z
+    chunks, a nonzero halo with a -0.0 (diagonal neighbours reach the halo's
+    edges and corners), and padded pitches, bit for bit against the oracle."""
+    u0, c, arr = inputs("27b", 70, 33, 41, seed=2)
+    rng = np.random.default_rng(2)
+    halo = np.ones(u0.shape, bool)
+    halo[1:-1, 1:-1, 1:-1] = False
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    u0[0, 0, 0] = -0.0
+    for dtype in ("f64", "f32"):
+        ref = oracle_run("27b", u0, c, arr, 4, dtype)
+        for p in ({"threads_x": 128, "threads_y": 2, "tile_z": 7}, {"threads_x": 64, "threads_y": 1, "tile_z": 200},
+                  {"threads_x": 256, "threads_y": 1, "tile_z": 16}, None):
+            print("box", dtype, p, flush=True)
+            got, _ = run_gpu("27b", dtype, u0, c, arr, 4, algo="naive", params=p)
+            assert_bitwise(got, ref, "box %s %s" % (dtype, p))
+        got, _ = run_gpu("27b", dtype, u0, c, arr, 4, algo="naive", pitch=(80, 40))
+        assert_bitwise(got, ref, "box padded %s" % dtype)
 
 
 @pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v", "25l"])
@@ -536,7 +557,8 @@ def test_mwd_odd_size_twin(stencil, dtype, n, T):
 
 @pytest.mark.parametrize("name,dtype", [("25pt-const-512", "f64"), ("25pt-var-384", "f64"), ("25pt-var-384", "f32"),
                                         ("7pt-var-256x512x1024", "f64"), ("7pt-var-256x512x1024", "f32"),
-                                        ("25pt-leapfrog-512", "f64"), ("25pt-leapfrog-512", "f32")])
+                                        ("25pt-leapfrog-512", "f64"), ("25pt-leapfrog-512", "f32"),
+                                        ("27pt-box-512", "f64")])
 def test_full_size_workloads(name, dtype):
     """The other workloads at their full sizes in their default launch
     configurations: the blocked sweep (where one exists) and the naive sweep
@@ -552,7 +574,7 @@ def test_full_size_workloads(name, dtype):
     g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
     coefs = [] if arr is None else [torch.from_numpy(a.astype(npdt)).to(dev) for a in arr]
     consts = None if c is None else [float(x) for x in c]
-    algos = ("mwd", "naive")
+    algos = ("naive",) if w.stencil == "27b" else ("mwd", "naive")
     res = {}
     for algo in algos:
         print("full size", name, dtype, algo, flush=True)

@@ -140,6 +140,25 @@ def test_candidates_cover_compiled_variants():
     G.girih_destroy(p)
 
 
+def test_box_plans():
+    """The 27-point box stencil: a naive plan streams the field pair (16 B per
+    update in FP64) with the cached variant by default; the plane-tile
+    variant and the blocked algorithm are refused."""
+    g = G.make_grid(64, 48, 40, 1)
+    c = (0.2, 0.05, 0.02, 0.01)
+    p = G.girih_plan("27b", "f64", g, c, "naive")
+    q, _, bytes_per_lup = G.girih_plan_info(p)
+    assert bytes_per_lup == 16.0 and q["variant"] == 0
+    G.girih_destroy(p)
+    for algo, params in (("mwd", None), ("naive", {"variant": 1, "threads_x": 64, "threads_y": 8})):
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan("27b", "f64", g, c, algo, params)
+        assert e.value.code == G.E_UNSUPPORTED
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("27b", "f64", G.make_grid(64, 48, 40, 2), c, "naive")   # halo != R
+    assert e.value.code == G.E_INVALID
+
+
 def test_leapfrog_plans():
     """The second-order-in-time 25-point stencil: naive plans stream four
     domain-sized arrays (V, U read and written, C); blocked plans default to
