@@ -73,3 +73,35 @@ def test_tuned_plan_matches_the_oracle(stencil, dtype):
     got, _ = run_gpu(stencil, dtype, u0, c, arr, 9, algo="mwd", params=best)
     ref = oracle_run(stencil, u0, c, arr, 9, dtype)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("stencil,dtype,n,T", [("7c", "f64", (256, 256, 256), 64), ("25c", "f32", (192, 192, 192), 32)])
+def test_tuned_rate_matches_timed_runs_of_the_problem(stencil, dtype, n, T):
+    """The tuner times the problem's own T-step schedule (every diamond row,
+    the clipped first and last included): its rate for a plan agrees with
+    back-to-back girih_run calls of that plan timed with HIP events, within
+    5 % (its own 3 % acceptance plus run-to-run noise)."""
+    import torch
+    from tests.gpu_util import upload
+    sw = plan(stencil, dtype, n)
+    q = sw.info()["params"]
+    sw.set_candidates([q])
+    _, rate = sw.tune("model", T, 30.0)
+    u0, c, arr = inputs(stencil, *n, seed=13)
+    b0 = upload(u0.astype(np.float64 if dtype == "f64" else np.float32))
+    b1 = b0.clone()
+    for _ in range(3):
+        sw.run(b0, b1, T)
+    times = []
+    s = torch.cuda.current_stream()
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        sw.run(b0, b1, T)
+        e1.record(s)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    run_rate = n[0] * n[1] * n[2] * T / sorted(times)[len(times) // 2] / 1e9
+    print("%s %s: tuner %.1f GLUP/s, timed runs %.1f" % (stencil, dtype, rate, run_rate), flush=True)
+    sw.close()
+    assert abs(run_rate / rate - 1.0) < 0.05
