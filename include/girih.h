@@ -246,6 +246,14 @@ int girih_tune_set_candidates(girih_plan_t plan, const girih_params* cands, int3
  * cap parameter sets into out (may be NULL to count) and their count to *n. */
 int girih_candidates(girih_plan_t plan, girih_params* out, int32_t cap, int32_t* n);
 
+/* The user's on-chip budget (paper, Section "Auto-tuning": the user gives the
+ * cache size, and candidates whose cache block does not fit it are pruned):
+ * MWD candidates whose workgroup needs more than `bytes` of LDS are left out
+ * of girih_candidates and of the exhaustive and hill-climbing searches.
+ * 0 (the default) = the CU's own 160 KiB, which every compiled shape fits.
+ * Negative: GIRIH_E_INVALID. */
+int girih_set_lds_budget(girih_plan_t plan, int64_t bytes);
+
 /* One measured tuner candidate. */
 typedef struct girih_tune_record {
     girih_params params;

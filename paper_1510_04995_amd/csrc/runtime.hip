@@ -9,12 +9,14 @@
 // order is the row barrier.
 //
 // Tuner (paper, Section "Auto-tuning"): it allocates its own arrays, times
-// candidates on test runs whose length is a multiple of diamond rows and is
-// doubled until two consecutive runs agree, and searches either every
-// feasible candidate or, per thread shape, by hill climbing over the diamond
-// width and the x tile.  The on-chip capacity bound (the paper prunes with
-// its cache block size model and the user's cache size) is exact here: only
-// compiled kernels whose LDS and registers fit exist in the table.
+// candidates on back-to-back runs of the problem's own T-step schedule, their
+// number doubled until two consecutive measurements agree, and searches
+// either every feasible candidate or, per thread shape, by hill climbing over
+// the diamond width, the wavefront depth and the x tile.  The on-chip
+// capacity bound (the paper prunes with its cache block size model and the
+// user's cache size) is exact here: only compiled kernels whose LDS and
+// registers fit exist in the table, and a user budget below the CU's LDS
+// prunes further (girih_set_lds_budget).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,6 +99,7 @@ struct girih_plan_s {
     int sched_device = -1;
     uint32_t sched_base = 1;
     uint32_t spin_limit = 1u << 20;
+    int64_t lds_budget = 0;   // tuner's on-chip budget (0: the CU's)
     // error word of the last run's bounded waits (null: the run had none)
     uint32_t* err_word = nullptr;
     Tuning tuning;
@@ -850,6 +853,7 @@ std::vector<girih_params> mwd_candidates(const girih_plan_s* p) {
     for (const auto& e : kernel_table()) {
         if (e.algo != AL_MWD || e.stencil != p->stencil || e.dtype != p->dtype || e.ns != 0) continue;
         if (e.xown_max < 8) continue;
+        if (p->lds_budget > 0 && e.lds_bytes > p->lds_budget) continue;
         // x tiles: the widest, and the widths that split nx into 1-3 more chunks
         std::set<int64_t> tiles;
         const int64_t nx = p->grid.nx;
@@ -1176,6 +1180,12 @@ int girih_plan_info(girih_plan_t p, girih_params* params, int64_t* lds_bytes, do
             *model_bytes_per_lup = 2 * s * R * ((2 * Dw - 2 * R) + (ND * Dw + 2 * R)) / (Dw * Dw);
         }
     }
+    return GIRIH_OK;
+}
+
+int girih_set_lds_budget(girih_plan_t p, int64_t bytes) {
+    if (!p || bytes < 0) return GIRIH_E_INVALID;
+    p->lds_budget = bytes;
     return GIRIH_OK;
 }
 

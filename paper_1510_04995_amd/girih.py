@@ -89,6 +89,7 @@ SIGNATURES = {
     "girih_plan_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GirihParams)]),
     "girih_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "girih_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "girih_set_lds_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "girih_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "girih_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "girih_destroy": (None, [ctypes.c_void_p]),
@@ -257,6 +258,10 @@ def girih_plan_info(plan):
 def girih_plan_set_params(plan, params):
     p = params if isinstance(params, GirihParams) else GirihParams.from_dict(params)
     _check(_lib().girih_plan_set_params(plan, ctypes.byref(p)), "girih_plan_set_params")
+
+
+def girih_set_lds_budget(plan, nbytes):
+    _check(_lib().girih_set_lds_budget(plan, int(nbytes)), "girih_set_lds_budget")
 
 
 def girih_set_wait_limit(plan, polls):

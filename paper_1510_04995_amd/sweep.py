@@ -100,6 +100,10 @@ class Sweep:
         s = stream if stream is not None else torch.cuda.current_stream()
         G.girih_check(self.plan, s.cuda_stream)
 
+    def set_lds_budget(self, nbytes):
+        """Prune tuner candidates whose workgroup needs more LDS (0: none)."""
+        G.girih_set_lds_budget(self.plan, nbytes)
+
     def set_wait_limit(self, polls):
         G.girih_set_wait_limit(self.plan, polls)
 

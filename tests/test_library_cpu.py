@@ -159,6 +159,30 @@ def test_box_plans():
     assert e.value.code == G.E_INVALID
 
 
+def test_lds_budget_prunes_candidates():
+    """The user's on-chip budget (the paper's cache size) leaves out every
+    candidate whose workgroup needs more LDS; 0 restores all of them."""
+    p = G.girih_plan("7c", "f64", G.make_grid(512, 512, 512, 1), (0.4, 0.1), "mwd")
+    every = G.girih_candidates(p)
+
+    def lds(q):
+        G.girih_plan_set_params(p, q)
+        return G.girih_plan_info(p)[1]
+    sizes = [lds(q) for q in every]
+    budget = 105000   # below the double-buffered Dw = 8 stage (106080 B), above Dw = 12's single one
+    G.girih_set_lds_budget(p, budget)
+    kept = G.girih_candidates(p)
+    assert 0 < len(kept) < len(every)
+    assert all(lds(q) <= budget for q in kept)
+    assert len(kept) == sum(1 for s in sizes if s <= budget)
+    G.girih_set_lds_budget(p, 0)
+    assert len(G.girih_candidates(p)) == len(every)
+    with pytest.raises(G.GirihError) as e:
+        G.girih_set_lds_budget(p, -1)
+    assert e.value.code == G.E_INVALID
+    G.girih_destroy(p)
+
+
 def test_leapfrog_plans():
     """The second-order-in-time 25-point stencil: naive plans stream four
     domain-sized arrays (V, U read and written, C); blocked plans default to
