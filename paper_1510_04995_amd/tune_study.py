@@ -2,6 +2,7 @@
 
   python -m paper_1510_04995_amd.tune_study [--out report.json] [--log train.jsonl]
   python -m paper_1510_04995_amd.tune_study summary <report.json> <out.md> <command...>
+  python -m paper_1510_04995_amd.tune_study tgs <train.jsonl> <out.md> <command...>
 
 1. The tuner measures every feasible blocked candidate (exhaustive search) of
    the training problems: 7-point constant 64^3 (T = 16) and 512^3 (T = 64),
@@ -17,7 +18,11 @@
    and tuning time.
 
 Prints one progress line per problem and a JSON report at the end; the
-`summary` form writes that report as a markdown table.
+`summary` form writes that report as a markdown table.  The `tgs` form
+writes, from the training records, the GPU counterpart of the paper's
+thread-group-size study: the best measured rate of each workgroup shape
+(waves per tile = row pairs x waves along x, cells per lane), over diamond
+widths, wavefront depths, x tiles and schedules.
 """
 import argparse
 import json
@@ -156,8 +161,43 @@ def summary(report_path, out_path, command):
         f.write("\n".join(lines) + "\n")
 
 
+def tgs(train_path, out_path, command):
+    """Best rate per (problem, workgroup shape) from the training records
+    (feature indices as in costmodel.features)."""
+    rows = [json.loads(line) for line in open(train_path) if line.strip()]
+    best = {}
+    for r in rows:
+        f = r["features"]
+        prob = (r["stencil"], r["dtype"], tuple(r["grid"]), r["T"])
+        dw, nf, tile = int(f[6]), int(f[7]), int(round(2 ** f[8]))
+        wx, pairs, vx = int(f[11]), int(f[12]), int(f[13])
+        variant = int(f[16]) + 2 * int(f[17])
+        shape = (pairs * wx, wx, vx)
+        cur = best.get((prob, shape))
+        if cur is None or r["glups"] > cur[0]:
+            best[(prob, shape)] = (r["glups"], dw, nf, tile, variant)
+    lines = ["# Workgroup shape study (the paper's thread-group sizes, on the GPU)", "",
+             "Command: `%s`" % command, "",
+             "From the tuner's exhaustive measurements of the training problems (every feasible candidate, "
+             "each timed on the problem's own T-step schedule): for each workgroup shape -- waves per tile "
+             "(= row pairs Dw/2 x waves along x), waves along x, x cells per lane -- the best GLUP/s over "
+             "diamond widths, wavefront depths, x tiles and schedule variants, and the candidate that reached "
+             "it.  A wave is 64 lanes; a tile is one workgroup on one CU.", "",
+             "| problem | waves per tile | waves along x | cells per lane | best GLUP/s | at (Dw, N_F, x tile, variant) |",
+             "|---|---|---|---|---|---|"]
+    for (prob, shape), (g, dw, nf, tile, variant) in sorted(best.items(), key=lambda kv: (kv[0][0], -kv[1][0])):
+        st, dt, grid, T = prob
+        lines.append("| %s %s %s, T = %d | %d | %d | %d | %.1f | (%d, %d, %d, %d) |"
+                     % (st, dt, "x".join(str(v) for v in grid), T, shape[0], shape[1], shape[2], g, dw, nf, tile,
+                        variant))
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "summary":
         summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif len(sys.argv) > 1 and sys.argv[1] == "tgs":
+        tgs(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     else:
         sys.exit(main())
