@@ -109,6 +109,11 @@ typedef struct girih_grid {
  *                        whose stage rows it reads or that read its own.
  *                        Either bit needs a shape compiled with it
  *                        (girih_candidates lists them).
+ *         With diamond_width, cells_per_lane, threads_x, wavefront_depth
+ *         and variant all zero, the library's default plan for the stencil
+ *         and precision is taken: its shape, depth and schedule (bit 0 set
+ *         for the 25-point constant and 7-point variable stencils in FP64,
+ *         where it measured faster).
  *  NAIVE: variant        0 = x/y neighbours through the caches (any block
  *                        of at most 256 threads, threads_x a multiple of 64),
  *                        1 = each plane's x/y neighbourhood staged in an LDS

@@ -175,8 +175,13 @@ const KernelEntry* find_naive(int st, int dt, int variant, int rows) {
 
 // Default MWD shape per radius and element size (diamond width, cells per
 // lane, waves along x); the tuner replaces it per problem.
-void default_mwd(int stencil, int R, int dtype, int& dw, int& vx, int& wx, int& nf) {
+void default_mwd(int stencil, int R, int dtype, int& dw, int& vx, int& wx, int& nf, int& var) {
     nf = 1;
+    var = 0;
+    // the dependency-driven schedule where it measured faster than row
+    // launches with the default shape: 25-point constant FP64 (429 tiles a
+    // row on 512^3, two rounds: +2 %) and 7-point variable FP64 (+4 %)
+    if (dtype == GIRIH_F64 && (stencil == GIRIH_25PT_CONST || stencil == GIRIH_7PT_VAR)) var = 1;
     if (stencil == GIRIH_25PT_LEAPFROG) {
         // the widest radius-4 diamond that fits (Dw = 8 moves more bytes than
         // the naive sweep); FP32: two planes per wavefront step (measured
@@ -234,8 +239,8 @@ int resolve(girih_plan_s* p, const girih_params* in) {
     const int R = p->R;
     if (p->algo == GIRIH_MWD) {
         int dw = q.diamond_width, vx = q.cells_per_lane, wx = q.threads_x ? q.threads_x / 64 : 0;
-        int ddw, dvx, dwx, dnf;
-        default_mwd(p->stencil, R, p->dtype, ddw, dvx, dwx, dnf);
+        int ddw, dvx, dwx, dnf, dvar;
+        default_mwd(p->stencil, R, p->dtype, ddw, dvx, dwx, dnf, dvar);
         if (q.threads_x < 0 || q.threads_x % 64 || vx < 0) return GIRIH_E_INVALID;
         if (dw == 0) dw = ddw;
         if (vx == 0 && wx == 0) { vx = dvx; wx = dwx; }
@@ -246,6 +251,8 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         const bool dflt_shape = q.diamond_width == 0 && q.cells_per_lane == 0 && q.threads_x == 0;
         const int nf = q.wavefront_depth ? q.wavefront_depth : (dflt_shape ? dnf : 1);
         if (nf < 0) return GIRIH_E_INVALID;
+        // (so is the default schedule: variant 0 with the default shape means "default")
+        if (dflt_shape && q.variant == 0 && q.wavefront_depth == 0) q.variant = dvar;
         // variant bit 0: dependency-driven schedule; bit 1: relaxed
         // synchronisation within the tile
         if (q.variant < 0 || q.variant > 3) return GIRIH_E_INVALID;

@@ -159,6 +159,23 @@ def test_box_plans():
     assert e.value.code == G.E_INVALID
 
 
+def test_default_schedules():
+    """The default plan takes the dependency-driven schedule (variant 1)
+    where it measured faster -- 25-point constant and 7-point variable in
+    FP64 -- and row launches elsewhere; a default shape asked for explicitly
+    keeps the variant it is given."""
+    cases = (("25c", "f64", 4, (0.2, 0.05, 0.04, 0.03, 0.0133), 1), ("7v", "f64", 1, None, 1),
+             ("7c", "f64", 1, (0.4, 0.1), 0), ("25c", "f32", 4, (0.2, 0.05, 0.04, 0.03, 0.0133), 0),
+             ("7v", "f32", 1, None, 0))
+    for st, dt, h, c, var in cases:
+        p = G.girih_plan(st, dt, G.make_grid(64, 64, 64, h), c, "mwd")
+        assert G.girih_plan_info(p)[0]["variant"] == var, (st, dt)
+        G.girih_destroy(p)
+    p = G.girih_plan("25c", "f64", G.make_grid(64, 64, 64, 4), cases[0][3], "mwd", {"diamond_width": 16})
+    assert G.girih_plan_info(p)[0]["variant"] == 0
+    G.girih_destroy(p)
+
+
 def test_lds_budget_prunes_candidates():
     """The user's on-chip budget (the paper's cache size) leaves out every
     candidate whose workgroup needs more LDS; 0 restores all of them."""
