@@ -164,13 +164,31 @@ class CostModel:
         return np.exp(y.cpu().numpy().astype(np.float64))
 
     def propose(self, sweep, T, k=5):
-        """The k candidates of a plan with the highest predicted throughput."""
+        """k candidates of a plan to measure.  Candidates are grouped by
+        workgroup shape (diamond width, waves along x, cells per lane) and
+        the shapes ranked by their best prediction; the k picks go round
+        robin over the shapes in that order, each shape's candidates in
+        predicted order: the best candidate of each of the k leading
+        shapes, or, where a problem has fewer shapes, their second-best
+        next.  The paper's tuner searches each thread-group shape on its
+        own; a model error about which shape is fastest -- the likeliest
+        error on a problem unlike the training problems -- then cannot take
+        all k measurements."""
         table = candidate_table(sweep, T)
         if not table:
             return []
         pred = self.predict([f for _, f in table])
-        order = np.argsort(-pred, kind="stable")[:k]
-        return [table[i][0] for i in order]
+        groups = {}
+        for i in np.argsort(-pred, kind="stable"):
+            q = table[i][0]
+            groups.setdefault((q["diamond_width"], q["threads_x"], q["cells_per_lane"]), []).append(int(i))
+        ranked = sorted(groups.values(), key=lambda g: -pred[g[0]])
+        picks = []
+        for r in range(k):
+            for g in ranked:
+                if r < len(g) and len(picks) < k:
+                    picks.append(g[r])
+        return [table[i][0] for i in picks]
 
 
 def tune_with_model(sweep, model, T, k=5, max_seconds=60.0):

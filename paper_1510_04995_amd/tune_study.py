@@ -60,7 +60,8 @@ def timed_tune(sw, mode, T, budget, cands=None):
     t0 = time.perf_counter()
     best, rate = sw.tune(mode, T, budget)
     return {"glups": rate, "measured": len(sw.tune_log()) - n0, "seconds": time.perf_counter() - t0,
-            "params": {k: best[k] for k in ("diamond_width", "wavefront_depth", "tile_x", "threads_x", "cells_per_lane")}}
+            "params": {k: best[k] for k in ("diamond_width", "wavefront_depth", "tile_x", "threads_x", "cells_per_lane",
+                                            "variant")}}
 
 
 def main():
@@ -140,14 +141,15 @@ def summary(report_path, out_path, command):
              "Evaluation on unseen problems: the GLUP/s of each search's pick, timed again after the "
              "searches with the four picks interleaved (three rounds, median), then the search's own best "
              "figure, the candidates it measured and its tuning seconds; pick = (diamond width, wavefront "
-             "depth, x tile, waves along x, cells per lane).", "",
+             "depth, x tile) waves along x x cells per lane, v = schedule / synchronisation variant.", "",
              "| problem | grid, T | exhaustive | hill climbing | model top-5 | largest tile that fits "
              "| model / exhaustive | model / hill climbing |", "|---|---|---|---|---|---|---|---|"]
     def pick(e):
         p = e.get("params", {})
         return "(%s)" % ", ".join(str(p.get(k, "")) for k in ("diamond_width", "wavefront_depth", "tile_x")
                                   if k in p) + ("" if "threads_x" not in p else
-                                                " %dx%d" % (p["threads_x"] // 64, p["cells_per_lane"]))
+                                                " %dx%d" % (p["threads_x"] // 64, p["cells_per_lane"])) + \
+            ("" if "variant" not in p else " v%d" % p["variant"])
     for r in rep["eval"]:
         def cell(k):
             e = r[k]

@@ -1,8 +1,9 @@
-"""The cost model's candidate features on the host: the traffic-model
-features against the paper's formulas as the oracle writes them
-(oracle/models.py), and the variant bits."""
+"""The cost model on the host: the traffic-model features against the
+paper's formulas as the oracle writes them (oracle/models.py), the variant
+bits, and how proposals spread over workgroup shapes."""
 import math
 
+import numpy as np
 import pytest
 
 from oracle import models
@@ -41,3 +42,38 @@ def test_the_seven_point_default_plan_features():
     assert 2 ** f[19] == pytest.approx(125 / 103)
     assert f[2] == f[3] == f[4] == 9.0 and f[15] == 6.0 and f[6] == 12.0
     assert math.isclose(f[14], 102960 / 65536)
+
+
+def test_proposals_go_round_robin_over_the_shapes():
+    """propose() groups candidates by workgroup shape, ranks the shapes by
+    their best prediction and takes the picks round robin over them: with a
+    stand-in predictor, k = 5 on a problem with more than five shapes gives
+    the best-predicted tile of the five leading shapes; on the 25-point
+    problem (three shapes) the best of each, then the second of the first
+    two."""
+    import paper_1510_04995_amd as P
+    shape = lambda q: (q["diamond_width"], q["threads_x"], q["cells_per_lane"])
+    m = C.CostModel.__new__(C.CostModel)      # no device: predict() replaced below
+
+    def predict(X):
+        X = np.asarray(X)
+        # shapes by diamond width, wider first, then waves and cells; larger x tiles first
+        return np.array([1000.0 * x[6] + 10.0 * x[11] + x[13] + 2 ** x[8] / 1000.0 for x in X])
+    m.predict = predict
+    sw = P.Sweep("7c", "f64", 512, 512, 512, [0.4, 0.1], "mwd")
+    picks = m.propose(sw, 64, 5)
+    table = C.candidate_table(sw, 64)
+    assert len({shape(p) for p, _ in table}) > 5
+    assert len(picks) == 5 and len({shape(q) for q in picks}) == 5
+    assert [q["diamond_width"] for q in picks] == sorted((q["diamond_width"] for q in picks), reverse=True)
+    for q in picks:
+        assert q["tile_x"] == max(p["tile_x"] for p, _ in table if shape(p) == shape(q))
+    sw.close()
+    sw = P.Sweep("25c", "f64", 512, 512, 512, [0.2, 0.05, 0.04, 0.03, 0.0133], "mwd")
+    table = C.candidate_table(sw, 32)
+    n_shapes = len({shape(p) for p, _ in table})
+    picks = m.propose(sw, 32, 5)
+    shapes = [shape(q) for q in picks]
+    assert n_shapes == 3 and len(picks) == 5
+    assert len(set(shapes[:3])) == 3 and shapes[3] == shapes[0] and shapes[4] == shapes[1]
+    sw.close()
