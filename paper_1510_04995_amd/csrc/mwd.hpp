@@ -1,4 +1,6 @@
-// Multi-threaded wavefront diamond (MWD) sweep: one launch per diamond row.
+// Multi-threaded wavefront diamond (MWD) sweep: one launch per diamond row
+// (mwd_row_kernel), or one launch of every row's tiles in dependency order
+// (mwd_sweep_kernel, further below).
 //
 // Paper: Section "Approach" (multi-dimensional intra-tile parallelisation,
 // the MWD listing and its description), Section "Diamond tiling", Section
@@ -54,6 +56,12 @@
 // stage are zero-filled once (halo lanes never write the stage) and halo
 // planes are set to zero; otherwise halo values are loaded where they are
 // needed (slower, same result).
+//
+// Within a wavefront step the waves synchronise with workgroup barriers, or
+// (SY = 1) wait only for the waves they share stage rows with.  Stencils
+// with coefficient arrays load a slot's coefficients with its neighbours;
+// the second-order-in-time stencil also reads, for each level, the level two
+// below at its own cell (mwd_tile).
 #pragma once
 #include <type_traits>
 

@@ -1,8 +1,9 @@
 """girih_run_noalloc (fixed device scratch, no allocation) against girih_run,
 through the C ABI: two calls in a row on one device, the second on a smaller
 grid, bit for bit; the blocked sweep of a constant- and a variable-coefficient
-stencil, and with relaxed synchronisation (whose error word sits in the fixed
-array too); a grid over the fixed limit is refused before any launch."""
+stencil, with relaxed synchronisation (whose error word sits in the fixed
+array too), and the second-order stencil (whose u^{-1} a run may copy into
+the fixed pair); a grid over the fixed limit is refused before any launch."""
 import numpy as np
 import pytest
 
@@ -23,10 +24,17 @@ def run_both(stencil, dtype, n, T, params):
     coefs = [upload(a.astype(npdt)) for a in (arr or [])]
     stream = torch.cuda.current_stream().cuda_stream
     out = []
+    prev = None
+    if stencil == "25l":   # u^{-1}: u^0's halo, a random interior
+        prev = u0.copy()
+        prev[h:-h, h:-h, h:-h] = np.random.default_rng(32).random(tuple(d - 2 * h for d in u0.shape))
     for fn in (G.girih_run, G.girih_run_noalloc):
         b0 = upload(u0.astype(npdt))
-        b1 = b0.clone()
-        b1[h:-h, h:-h, h:-h] = float("nan")
+        if prev is None:
+            b1 = b0.clone()
+            b1[h:-h, h:-h, h:-h] = float("nan")
+        else:
+            b1 = upload(prev.astype(npdt))
         print(fn.__name__, stencil, dtype, n, T, flush=True)
         idx = fn(plan, b0.data_ptr(), b1.data_ptr(), [t.data_ptr() for t in coefs], T, stream)
         torch.cuda.synchronize()
@@ -37,7 +45,8 @@ def run_both(stencil, dtype, n, T, params):
 
 @pytest.mark.parametrize("stencil,dtype,params", [("7c", "f64", {"diamond_width": 8}),
                                                   ("7v", "f32", {"diamond_width": 12}),
-                                                  ("7c", "f64", {"variant": 2})])
+                                                  ("7c", "f64", {"variant": 2}),
+                                                  ("25l", "f64", {})])
 def test_noalloc_equals_run_twice_second_smaller(stencil, dtype, params):
     for n, T in (((150, 61, 23), 11), ((70, 29, 9), 6)):
         ref, got = run_both(stencil, dtype, n, T, params)
