@@ -27,8 +27,8 @@ Beside the headline value the line carries:
                 the FP64 result, measured outside the timed region;
   per_stencil   every other workload of the study (25-point constant 512^3,
                 25-point variable 384^3, 7-point variable 256x512x1024, the
-                second-order 25-point stencil on 512^3; the 27-point box
-                stencil on 512^3, naive only), blocked
+                second-order 25-point stencil on 512^3, the 27-point box
+                stencil on 512^3), blocked
                 and naive, FP64 and FP32, timed the same way outside the timed
                 region, with the FP32 error against the FP64 blocked result
                 (which equals the FP64 oracle bit for bit, as the GPU parity
@@ -166,8 +166,7 @@ def per_stencil(torch, dev, reps=3):
     for name in ("25pt-const-512", "25pt-var-384", "7pt-var-256x512x1024", "25pt-leapfrog-512", "27pt-box-512"):
         w = WORKLOADS[name]
         h = w.radius
-        # (the box stencil has the naive sweep only)
-        algos = ("naive",) if w.stencil == "27b" else ("mwd", "naive")
+        algos = ("mwd", "naive")
         log("inputs " + name)
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0)
         consts = None if c is None else [float(x) for x in c]

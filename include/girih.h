@@ -61,7 +61,9 @@ typedef enum {
                              * ((c0*V + c1*F) + c2*E) + c3*K with F, E, K the
                              * sums of the 6 face, 12 edge and 8 corner
                              * neighbours, each in lexicographic order of the
-                             * offset (dz, dy, dx); naive sweep only */
+                             * offset (dz, dy, dx); blocked at Dw = 8
+                             * (FP32 also 12), wavefront depth 1, row
+                             * launches */
 } girih_stencil;
 
 typedef enum { GIRIH_F64 = 0, GIRIH_F32 = 1 } girih_dtype;
@@ -70,11 +72,12 @@ typedef enum {
     GIRIH_NAIVE = 0, /* T launches of one full-domain Jacobi step              */
     GIRIH_MWD = 1    /* diamond rows: one launch per row of diamond tiles      */
 } girih_algo;
-/* GIRIH_MWD exists for the five star stencils, in the diamond shapes
- * compiled for them (girih_candidates); girih_plan returns
- * GIRIH_E_UNSUPPORTED for a shape that was not compiled, and for
- * GIRIH_27PT_BOX.  For the second-order-in-time stencil a level also reads
- * the level two below it at its own cell. */
+/* GIRIH_MWD exists for every stencil, in the diamond shapes compiled for it
+ * (girih_candidates); girih_plan returns GIRIH_E_UNSUPPORTED for a shape that
+ * was not compiled.  For the second-order-in-time stencil a level also reads
+ * the level two below it at its own cell.  For the box stencil a level reads
+ * the level below at three planes of the neighbouring rows: its levels are
+ * skewed by two planes along z, and a stage row holds those three planes. */
 
 /* Grid descriptor, in elements. */
 typedef struct girih_grid {

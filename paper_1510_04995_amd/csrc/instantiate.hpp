@@ -78,11 +78,15 @@ hipError_t launch_naive_box(const void* args, dim3 grid, dim3 block, hipStream_t
     return hipGetLastError();
 }
 
-// The 27-point box stencil: the cached naive sweep (variant 0).
+// The 27-point box stencil: the cached naive sweep (variant 0) and the
+// blocked sweep with its three-plane stage rows (one CU holds them at Dw = 8
+// in FP64, 159 of 160 KiB, and up to Dw = 12 in FP32).
 template <typename Real>
 void add_box_family(std::vector<KernelEntry>& t, int st, int dt) {
     t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0, 0,
                             reinterpret_cast<const void*>(&naive_box_kernel<Real>), &launch_naive_box<Real>});
+    add_mwd<Stencil27B, Real, 8, 1, 2, 1, false, 0>(t, st, dt);
+    if constexpr (sizeof(Real) == 4) add_mwd<Stencil27B, Real, 12, 1, 2, 1, false, 0>(t, st, dt);
 }
 
 template <class S, typename Real>

@@ -252,9 +252,18 @@ struct MwdKernel {
     // consecutive planes per level); the z radius in slabs, and the skew of
     // the levels in slabs, is RZ = ceil(R / NF).
     static_assert(NF >= 1 && NF <= 4, "wavefront depth");
-    static constexpr int RZ = (R + NF - 1) / NF;
-    // a stage row holds the NF planes of a slab, one sub-row each
-    static constexpr int SROW = NF * XLP;
+    // Box stencils read the level below at planes p-1, p, p+1 of the rows
+    // beside their own: the levels are skewed by two planes (so that plane
+    // p+1 is finished a step before it is read) and a stage row holds the
+    // three planes, one sub-row each.  (Radius 1, one plane per step.)
+    static constexpr bool BOX = S::BOX;
+    static_assert(!BOX || (R == 1 && NF == 1), "box stencils: radius 1, one plane per step");
+    static constexpr int RZ = BOX ? 2 : (R + NF - 1) / NF;
+    // sub-rows of a stage row: the NF planes of a slab, or a box stencil's three
+    static constexpr int SUB = BOX ? 3 : NF;
+    // planes a duty stream (stage rows loaded from HBM) brings per step
+    static constexpr int DP = BOX ? 3 : NF;
+    static constexpr int SROW = SUB * XLP;
     // one stage buffer: stage rows plus 2R+1 spare rows that absorb the stage
     // writes and reads of slots without a stage row
     static constexpr int BUF_ROWS = Sh::STAGE_ROWS + 2 * R + 1;
@@ -442,7 +451,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
     // registers hold no halo values), where they are read from the stage.
     // (FP32 kernels, two stage buffers, lose with it; radius 4 would need
     // eight moves per value.)
-    constexpr bool XDPP = R == 1 && sizeof(Real) == 8;
+    constexpr bool XDPP = R == 1 && sizeof(Real) == 8 && !KK::BOX;
     bool mxm[VX], mxp[VX];
     auto in_halo = [&](int x) { return (x >= -R && x < 0) || (x >= nx && x < nx + R); };
 #pragma unroll
@@ -657,7 +666,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
 #pragma unroll
             for (int v = 0; v < VX; ++v)
                 if (hz[v])
-                    for (int row = 0; row < KK::LDS_ROWS * NF; ++row) stage[row * XLP + R + cb + lane + 64 * v] = Real(0);
+                    for (int row = 0; row < KK::LDS_ROWS * KK::SUB; ++row) stage[row * XLP + R + cb + lane + 64 * v] = Real(0);
         }
 
         // wavefront steps end here: the last slab of level L-1 (slab nzq-1) is
@@ -676,18 +685,20 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
         auto lds = [&](uint32_t byte_addr) -> Real& {
             return *reinterpret_cast<Real*>(reinterpret_cast<char*>(stage) + byte_addr);
         };
-        auto put = [&](uint32_t la, const Real (&src)[NF][VX]) {   // la: per-lane LDS byte address
+        constexpr int DP = KK::DP;
+        auto put = [&](uint32_t la, const Real (&src)[DP][VX]) {   // la: per-lane LDS byte address
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
+            for (int f = 0; f < DP; ++f)
 #pragma unroll
                 for (int v = 0; v < VX; ++v)
                     if (!hz[v]) lds(la + (f * XLP + 64 * v) * SB) = src[f][v];
         };
-        // x-halo columns of a staged computed row (slab q) when the halo is not zero
+        // x-halo columns of a staged computed row (slab q; a box stencil's
+        // planes q-1 .. q+1) when the halo is not zero
         auto fix_halo_cols = [&](int li, int q, int y) {   // li: element index, buffer included
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const int pl = NF * q + f;
+            for (int f = 0; f < KK::SUB; ++f) {
+                const int pl = KK::BOX ? q - 1 + f : NF * q + f;
                 if (pl < -R || pl >= nz + R) continue;
                 const Real* base = at(a.in[0], plane_off(pl) + (int64_t)(y + hh) * pitchx * SB);
 #pragma unroll
@@ -698,8 +709,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
 
         // Loads of step zs + PD's inputs (see the streams above); with a
         // staging function, duty registers are first staged.
-        auto prefetch = [&](int zs, bool steady, Real (&vA)[NF][VX], Real (&vB)[NF][VX], Real (&dA2)[NF][VX],
-                            Real (&dB2)[NF][VX], Real (&rA)[NF][VX], Real (&rB)[NF][VX], Real (&wA)[NF][VX],
+        auto prefetch = [&](int zs, bool steady, Real (&vA)[NF][VX], Real (&vB)[NF][VX], Real (&dA2)[DP][VX],
+                            Real (&dB2)[DP][VX], Real (&rA)[DP][VX], Real (&rB)[DP][VX], Real (&wA)[NF][VX],
                             Real (&wB)[NF][VX], auto&& stage_fn) __attribute__((always_inline)) {
             const int f = (int)fresh_s((uint32_t)flags);
             // per-lane offsets, formed here from the uniform parts (fresh
@@ -728,12 +739,28 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                     for (int v = 0; v < VX; ++v) dst[f][v] = ld_at(base, o[v]);
                 }
             };
+            // duty streams: the NF planes of the slab, or a box stencil's
+            // planes p-1 .. p+1 around its plane p (inside the haloed grid in
+            // the steady range: p+1 is at least one slab below zs + PD)
+            auto fetchd = [&](bool odd, int dz, const uint32_t (&o)[VX], Real (&dst)[DP][VX]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int f = 0; f < DP; ++f) {
+                    const int df = KK::BOX ? f - 1 : f;
+                    if (!steady) {
+                        const int q = NF * (zs + PD - RZ * dz) + df;
+                        if (q < -R || q >= nz + R) continue;
+                    }
+                    const Real* base = at(odd ? fb1 : fb0, (int64_t)df * plane_b);
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) dst[f][v] = ld_at(base, o[v]);
+                }
+            };
             if (f & (F_CMP_A | F_D1_A)) fetch(f & F_PV_A, kvA, oA, vA);
             if (f & (F_CMP_B | F_D1_B)) fetch(f & F_PV_B, kvB, oB, vB);
-            if (f & F_D2_A) { stage_fn(fresh_s(uA2) + lane_b, dA2); fetch(!(f & F_PV_A), kvA, oA, dA2); }
-            if (f & F_D2_B) { stage_fn(fresh_s(uB2) + lane_b, dB2); fetch(!(f & F_PV_B), kvB, oB, dB2); }
-            if (f & F_O_A) { stage_fn(fresh_s(uOA) + lane_b, rA); fetch(f & F_PT, H, oOA, rA); }
-            if (f & F_O_B) { stage_fn(fresh_s(uOB) + lane_b, rB); fetch(f & F_PT, H, oOB, rB); }
+            if (f & F_D2_A) { stage_fn(fresh_s(uA2) + lane_b, dA2); fetchd(!(f & F_PV_A), kvA, oA, dA2); }
+            if (f & F_D2_B) { stage_fn(fresh_s(uB2) + lane_b, dB2); fetchd(!(f & F_PV_B), kvB, oB, dB2); }
+            if (f & F_O_A) { stage_fn(fresh_s(uOA) + lane_b, rA); fetchd(f & F_PT, H, oOA, rA); }
+            if (f & F_O_B) { stage_fn(fresh_s(uOB) + lane_b, rB); fetchd(f & F_PT, H, oOB, rB); }
             if constexpr (S::LEAPFROG) {
                 // level kf-2 of a computing row: the time level of parity
                 // opposite to kv's, slab zs + PD - RZ*kf
@@ -755,19 +782,25 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
         // Prefetch registers, one set per step parity.  qA/qB: the input level
         // kv of a row (its input ring);
         // p2: duty level kv-1; po: the out-of-span row.
-        Real qA[PD][NF][VX], qB[PD][NF][VX], p2A[PD][NF][VX], p2B[PD][NF][VX], poA[PD][NF][VX], poB[PD][NF][VX];
+        Real qA[PD][NF][VX], qB[PD][NF][VX], p2A[PD][DP][VX], p2B[PD][DP][VX], poA[PD][DP][VX], poB[PD][DP][VX];
         // second-order-in-time stencils: level kf-2 of each row (the first
         // computed level's previous time level)
         Real uA[PD][NF][VX], uB[PD][NF][VX];
         // copied levels (row A / B, input array 0 / 1) of slab zs + PD
         Real cpv[PD][2][2][NF][VX];
 #pragma unroll
+        for (int f = 0; f < DP; ++f)
+#pragma unroll
+            for (int v = 0; v < VX; ++v)
+#pragma unroll
+                for (int c = 0; c < PD; ++c) p2A[c][f][v] = p2B[c][f][v] = poA[c][f][v] = poB[c][f][v] = Real(0);
+#pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
 #pragma unroll
                 for (int c = 0; c < PD; ++c) {
-                    qA[c][f][v] = qB[c][f][v] = p2A[c][f][v] = p2B[c][f][v] = poA[c][f][v] = poB[c][f][v] = Real(0);
+                    qA[c][f][v] = qB[c][f][v] = Real(0);
                     uA[c][f][v] = uB[c][f][v] = Real(0);
                     cpv[c][0][0][f][v] = cpv[c][0][1][f][v] = cpv[c][1][0][f][v] = cpv[c][1][1][f][v] = Real(0);
                 }
@@ -843,9 +876,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                     if (!hz[v]) {
                         static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
                             constexpr int s = decltype(sc)::value;
+                            if constexpr (KK::BOX) {
+                                // planes p-1, p, p+1 of the level: ring positions RZ-1 .. RZ+1
 #pragma unroll
-                            for (int g = 0; g < NF; ++g)
-                                lds(lcs[s] + BOFF + CORNER + (g * XLP + 64 * v) * SB) = ring[s][P(RZ)][g][v];
+                                for (int d = 0; d < 3; ++d)
+                                    lds(lcs[s] + BOFF + CORNER + (d * XLP + 64 * v) * SB) = ring[s][P(RZ - 1 + d)][0][v];
+                            } else {
+#pragma unroll
+                                for (int g = 0; g < NF; ++g)
+                                    lds(lcs[s] + BOFF + CORNER + (g * XLP + 64 * v) * SB) = ring[s][P(RZ)][g][v];
+                            }
                         });
                     }
                 }
@@ -857,7 +897,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                 // next load is issued.
                 prefetch(zs, STEADY, qA[ph % PD], qB[ph % PD], p2A[ph % PD], p2B[ph % PD], poA[ph % PD], poB[ph % PD],
                          uA[ph % PD], uB[ph % PD],
-                         [&](uint32_t la, const Real (&src)[NF][VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
+                         [&](uint32_t la, const Real (&src)[DP][VX]) __attribute__((always_inline)) { put(la + BOFF, src); });
                 if constexpr (CPF) {
                     const int q = zs + PD;   // the slab the copy stores at step zs + PD
                     if ((f & (F_COPY_A | F_COPY_B)) && q >= 0 && NF * q < nz) {
@@ -894,8 +934,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                             for (int j = Sh::sl_lo(k); j < Sh::sl_lo(k) + Sh::nrows(k); ++j) {
                                 const int y = ybase + j;
                                 if (!((y >= -R && y < 0) || (y >= ny && y < ny + R))) continue;
-                                for (int g = 0; g < NF; ++g) {
-                                    const int q = NF * (zs - RZ * (k + 1)) + g;
+                                for (int g = 0; g < KK::SUB; ++g) {
+                                    const int q = KK::BOX ? zs - RZ * (k + 1) - 1 + g : NF * (zs - RZ * (k + 1)) + g;
                                     if (q < -R || q >= nz + R) continue;
                                     const Real* base = at(a.in[0], plane_off(q) + (int64_t)(y + hh) * pitchx * SB);
                                     const int li = lds_row(k, j) + BOFE + g * XLP;
@@ -940,7 +980,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
 #pragma unroll
                             for (int v = 0; v < VX; ++v)
                                 buf_store((i & 1) ? rs_odd : rs_even, (sgo[i][v] + g * plane_b) | zd,
-                                          lds(stl[i] + BOFF + (g * XLP + 64 * v) * SB));
+                                          lds(stl[i] + BOFF + ((KK::BOX ? 1 : g) * XLP + 64 * v) * SB));
                         }
                     }
                 };
@@ -997,9 +1037,10 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                             }
                         }
                     }
+                    // (box stencils read their neighbourhood in the slot itself)
                     const uint32_t lb = lcs[t - 1] + BOFF;     // corner of (level - 1, row)
 #pragma unroll
-                    for (int g = 0; g < NF; ++g) {
+                    for (int g = 0; g < (KK::BOX ? 0 : NF); ++g) {
 #pragma unroll
                         for (int v = 0; v < VX; ++v) {
                             const uint32_t c0 = lb + (g * XLP + 64 * v) * SB + CORNER;
@@ -1062,40 +1103,57 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
                                 const bool zv = ((cm & zS[g]) >> s) & 1u;
 #pragma unroll
                                 for (int v = 0; v < VX; ++v) {
-                                    Nbhd<Real, R> n;
-                                    n.c = ring[s - 1][P(RZ)][g][v];
-                                    if constexpr (S::LEAPFROG) {
-                                        // the first computed level of a row takes
-                                        // level kf-2 from its HBM stream
-                                        if constexpr (s == 1)
-                                            n.uo = vuA[g][v];
-                                        else if constexpr (SBK >= 0)
-                                            n.uo = s == SBK + 1 ? vuB[g][v] : uold[g][v];
-                                        else
-                                            n.uo = s == sb + 1 ? vuB[g][v] : uold[g][v];
-                                    }
+                                    if constexpr (KK::BOX) {
+                                        // the 3x3x3 box of level k-1: the own column from the
+                                        // ring (planes p-1, p, p+1 at positions RZ-1 .. RZ+1),
+                                        // the rest from the stage (sub-row dz+1 holds plane p+dz)
+                                        Box27<Real> bx;
+                                        const uint32_t c0 = lcs[s - 1] + BOFF + 64 * v * SB + CORNER;
 #pragma unroll
-                                    for (int r = 1; r <= R; ++r) {
-                                        // plane g -/+ r of the slab: slab offset floor((g -/+ r) / NF),
-                                        // plane within it; ring position RZ + that offset, where
-                                        // position 2*RZ is the slab slot s-1 computed this step
-                                        const int dm = g - r, dp = g + r;
-                                        const int sm = dm >= 0 ? dm / NF : -((-dm + NF - 1) / NF);
-                                        const int sp = dp / NF;
-                                        n.zm[r - 1] = ring[s - 1][P(RZ + sm)][dm - sm * NF][v];
-                                        n.zp[r - 1] = RZ + sp == RING ? prev[dp - sp * NF][v]
-                                                                      : ring[s - 1][P(RZ + sp)][dp - sp * NF][v];
-                                        n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][g][v];
-                                        n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][g][v];
-                                        n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][g][v];
-                                        n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][g][v];
-                                    }
-                                    Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
-                                    if constexpr (S::NCOEF > 0) {
+                                        for (int m = 0; m < 27; ++m) {
+                                            const int dz = m / 9 - 1, dy = (m / 3) % 3 - 1, dx = m % 3 - 1;
+                                            if (dy == 0 && dx == 0)
+                                                bx.v[m] = ring[s - 1][P(RZ + dz)][0][v];
+                                            else
+                                                bx.v[m] = lds(c0 + ((dz + 1) * XLP + dy * SROW + dx) * SB);
+                                        }
+                                        nv[g][v] = Stencil27B::apply_box(bx, a.coef.k);
+                                    } else {
+                                        Nbhd<Real, R> n;
+                                        n.c = ring[s - 1][P(RZ)][g][v];
+                                        if constexpr (S::LEAPFROG) {
+                                            // the first computed level of a row takes
+                                            // level kf-2 from its HBM stream
+                                            if constexpr (s == 1)
+                                                n.uo = vuA[g][v];
+                                            else if constexpr (SBK >= 0)
+                                                n.uo = s == SBK + 1 ? vuB[g][v] : uold[g][v];
+                                            else
+                                                n.uo = s == sb + 1 ? vuB[g][v] : uold[g][v];
+                                        }
 #pragma unroll
-                                        for (int m = 0; m < S::NCOEF; ++m) cf[m] = cfp[s % (LDEP + 1)][m][g][v];
+                                        for (int r = 1; r <= R; ++r) {
+                                            // plane g -/+ r of the slab: slab offset floor((g -/+ r) / NF),
+                                            // plane within it; ring position RZ + that offset, where
+                                            // position 2*RZ is the slab slot s-1 computed this step
+                                            const int dm = g - r, dp = g + r;
+                                            const int sm = dm >= 0 ? dm / NF : -((-dm + NF - 1) / NF);
+                                            const int sp = dp / NF;
+                                            n.zm[r - 1] = ring[s - 1][P(RZ + sm)][dm - sm * NF][v];
+                                            n.zp[r - 1] = RZ + sp == RING ? prev[dp - sp * NF][v]
+                                                                          : ring[s - 1][P(RZ + sp)][dp - sp * NF][v];
+                                            n.xp[r - 1] = nb[s % (LDEP + 1)][r - 1][g][v];
+                                            n.xm[r - 1] = nb[s % (LDEP + 1)][R + r - 1][g][v];
+                                            n.yp[r - 1] = nb[s % (LDEP + 1)][2 * R + r - 1][g][v];
+                                            n.ym[r - 1] = nb[s % (LDEP + 1)][3 * R + r - 1][g][v];
+                                        }
+                                        Real cf[S::NCOEF > 0 ? S::NCOEF : 1];
+                                        if constexpr (S::NCOEF > 0) {
+#pragma unroll
+                                            for (int m = 0; m < S::NCOEF; ++m) cf[m] = cfp[s % (LDEP + 1)][m][g][v];
+                                        }
+                                        nv[g][v] = S::apply(n, a.coef.k, cf);
                                     }
-                                    nv[g][v] = S::apply(n, a.coef.k, cf);
                                 }
                                 if constexpr (!STEADY) {
                                     // a level whose plane is a halo plane (or beyond) holds the halo
@@ -1211,7 +1269,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<Real>& a, const int64_t r
         const int zB0 = zB1 < zB2 ? zB1 : zB2;
         const int zB = (zB0 / UNR) * UNR > zA ? (zB0 / UNR) * UNR : zA;
         // first loads: the inputs of steps -RING and -RING + 1
-        auto no_stage = [](uint32_t, const Real (&)[NF][VX]) {};
+        auto no_stage = [](uint32_t, const Real (&)[DP][VX]) {};
         static_for<0, PD>([&](auto pc) __attribute__((always_inline)) {
             constexpr int c = decltype(pc)::value;
             prefetch(-RING - PD + c, false, qA[c], qB[c], p2A[c], p2B[c], poA[c], poB[c], uA[c], uB[c], no_stage);

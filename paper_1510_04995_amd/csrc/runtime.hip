@@ -182,7 +182,12 @@ void default_mwd(int stencil, int R, int dtype, int& dw, int& vx, int& wx, int& 
     // launches with the default shape: 25-point constant FP64 (429 tiles a
     // row on 512^3, two rounds: +2 %) and 7-point variable FP64 (+4 %)
     if (dtype == GIRIH_F64 && (stencil == GIRIH_25PT_CONST || stencil == GIRIH_7PT_VAR)) var = 1;
-    if (stencil == GIRIH_25PT_LEAPFROG) {
+    if (stencil == GIRIH_27PT_BOX) {
+        // the widest box diamond whose three-plane stage fits one CU in FP64
+        dw = 8;
+        vx = 1;
+        wx = 2;
+    } else if (stencil == GIRIH_25PT_LEAPFROG) {
         // the widest radius-4 diamond that fits (Dw = 8 moves more bytes than
         // the naive sweep); FP32: two planes per wavefront step (measured
         // 32 % faster on 512^3)
@@ -261,7 +266,7 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         if ((q.variant & 1) && !k->launch_sweep) return GIRIH_E_UNSUPPORTED;
         // the kernel addresses a window of nf*(RZ*(L+1)+1) planes (RZ = ceil(R/nf))
         // with 32-bit offsets
-        const int64_t rz = (R + nf - 1) / nf;
+        const int64_t rz = p->stencil == GIRIH_27PT_BOX ? 2 : (R + nf - 1) / nf;   // level skew in slabs
         const int64_t win = (int64_t)nf * (rz * (dw / R + 1) + 1);
         if (win * p->grid.pitch_y * p->grid.pitch_x * (int64_t)elem_bytes(p->dtype) >= (int64_t)1 << 31)
             return GIRIH_E_UNSUPPORTED;

@@ -30,7 +30,8 @@ namespace girih {
 
 // Neighbourhood of one point: centre, and for r = 1..R the six axis
 // neighbours; uo is the point's previous value (second-order-in-time stencils
-// only; LEAPFROG says whether a stencil reads it).
+// only; LEAPFROG says whether a stencil reads it).  BOX: the stencil reads
+// the whole 3x3x3 box (Box27 below) instead.
 template <typename Real, int R>
 struct Nbhd {
     Real c;
@@ -41,6 +42,7 @@ struct Nbhd {
 struct Stencil7C {
     static constexpr int R = 1, NCOEF = 0, NCONST = 2;
     static constexpr bool LEAPFROG = false;
+    static constexpr bool BOX = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 1>& n, const Real* k, const Real*) {
         return ((k[0] * n.c + k[1] * (n.xp[0] + n.xm[0])) + k[1] * (n.yp[0] + n.ym[0]))
@@ -51,6 +53,7 @@ struct Stencil7C {
 struct Stencil7V {
     static constexpr int R = 1, NCOEF = 7, NCONST = 0;
     static constexpr bool LEAPFROG = false;
+    static constexpr bool BOX = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 1>& n, const Real*, const Real* C) {
         Real u = C[0] * n.c;
@@ -67,6 +70,7 @@ struct Stencil7V {
 struct Stencil25C {
     static constexpr int R = 4, NCOEF = 0, NCONST = 5;
     static constexpr bool LEAPFROG = false;
+    static constexpr bool BOX = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 4>& n, const Real* k, const Real*) {
         Real u = k[0] * n.c;
@@ -86,6 +90,7 @@ struct Stencil25C {
 struct Stencil25V {
     static constexpr int R = 4, NCOEF = 13, NCONST = 0;
     static constexpr bool LEAPFROG = false;
+    static constexpr bool BOX = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 4>& n, const Real*, const Real* C) {
         Real u = C[0] * n.c;
@@ -102,6 +107,7 @@ struct Stencil25V {
 struct Stencil25L {
     static constexpr int R = 4, NCOEF = 1, NCONST = 5;
     static constexpr bool LEAPFROG = true;
+    static constexpr bool BOX = false;
     template <typename Real>
     __device__ __forceinline__ static Real apply(const Nbhd<Real, 4>& n, const Real* k, const Real* C) {
         Real b = k[0] * n.c;
@@ -127,6 +133,7 @@ struct Box27 {
 struct Stencil27B {
     static constexpr int R = 1, NCOEF = 0, NCONST = 4;
     static constexpr bool LEAPFROG = false;
+    static constexpr bool BOX = true;
     template <typename Real>
     __device__ __forceinline__ static Real apply_box(const Box27<Real>& b, const Real* k) {
         // class of offset m: number of nonzero components (compile-time)

@@ -15,8 +15,7 @@
       8 TB/s: the field read and written, the coefficient arrays, and for the
       second-order-in-time stencil the previous level read as well).
 
-The blocked sweep serves every stencil but the 27-point box, which runs the
-naive sweep only.  One more case is
+One more case is
 one GPU's share of the 512^3 7-point problem split in y across two GPUs
 (512 x 256 x 512), the shape a y-slab decomposition gives each device.
 """
@@ -62,7 +61,7 @@ def run(reps):
         u0, c, arr = field_and_coefs(w.stencil, w.nx, w.ny, w.nz, seed=0, const_coefs=w.const_coefs)
         consts = None if c is None else [float(x) for x in c]
         ref = None
-        algos = ("naive",) if w.stencil == "27b" else ("naive", "mwd")
+        algos = ("naive", "mwd")
         for dt in w.dtypes:
             npdt = np.float64 if dt == "f64" else np.float32
             g0 = _grid(u0.astype(npdt), torch, dev)

@@ -212,6 +212,11 @@ MWD_CASES = [
     ("25v", "f32", 8, 1, 2, 0, (130, 40, 19), [3]),
     ("25v", "f32", 8, 2, 1, 0, (250, 26, 18), [3]),
     ("25v", "f32", 16, 1, 1, 0, (100, 45, 21), [2, 3, 7]),
+    ("27b", "f64", 8, 1, 2, 0, (150, 45, 19), [1, 2, 3, 4, 5, 9, 13]),
+    ("27b", "f64", 8, 1, 2, 22, (131, 37, 21), [6]),
+    ("27b", "f32", 8, 1, 2, 0, (140, 30, 20), [3, 8]),
+    ("27b", "f32", 12, 1, 2, 0, (200, 50, 25), [1, 5, 7, 14]),
+    ("27b", "f32", 12, 1, 2, 40, (131, 50, 12), [7, 16]),
 ]
 
 
@@ -574,7 +579,7 @@ def test_full_size_workloads(name, dtype):
     g0 = torch.from_numpy(u0.astype(npdt)).to(dev)
     coefs = [] if arr is None else [torch.from_numpy(a.astype(npdt)).to(dev) for a in arr]
     consts = None if c is None else [float(x) for x in c]
-    algos = ("naive",) if w.stencil == "27b" else ("mwd", "naive")
+    algos = ("mwd", "naive")
     res = {}
     for algo in algos:
         print("full size", name, dtype, algo, flush=True)
@@ -597,11 +602,12 @@ def test_full_size_workloads(name, dtype):
                                                   ("25c", 16, 1, 1, (120, 45, 19), 5),
                                                   ("7c", 8, 2, 1, (131, 29, 11), 7),
                                                   ("25v", 8, 2, 1, (290, 21, 17), 3),
-                                                  ("25c", 8, 2, 1, (290, 21, 17), 3)])
+                                                  ("25c", 8, 2, 1, (290, 21, 17), 3),
+                                                  ("27b", 8, 1, 2, (140, 37, 13), 9)])
 def test_mwd_nonzero_halo(stencil, dw, vx, wx, n, T):
     """Arbitrary fixed Dirichlet values (and a -0.0) in the halo take the general path."""
     u0, c, arr = inputs(stencil, *n, seed=8)
-    h = 1 if stencil.startswith("7") else 4
+    h = 4 if stencil.startswith("25") else 1
     rng = np.random.default_rng(3)
     halo = np.ones(u0.shape, dtype=bool)
     halo[h:-h, h:-h, h:-h] = False
@@ -612,6 +618,28 @@ def test_mwd_nonzero_halo(stencil, dw, vx, wx, n, T):
     assert_bitwise(got, oracle_run(stencil, u0, c, arr, T), "nonzero halo %s" % stencil)
     got32, _ = run_gpu(stencil, "f32", u0, c, arr, T, algo="mwd", params=mwd_params(dw, vx, wx))
     assert_bitwise(got32, oracle_run(stencil, u0, c, arr, T, "f32"), "nonzero halo f32 %s" % stencil)
+
+
+def test_mwd_box_thin_grids_and_random_shapes():
+    """The blocked box stencil on grids thinner than a diamond, a z-slab or
+    the two-plane level skew, then on seeded random grids and step counts in
+    every compiled shape: equal to the oracle bit for bit."""
+    for dtype in ("f64", "f32"):
+        for n in ((1, 1, 1), (9, 5, 3), (33, 7, 2), (130, 3, 1), (70, 1, 4)):
+            u0, c, arr = inputs("27b", *n, seed=17)
+            print("mwd box thin", dtype, n, flush=True)
+            got, _ = run_gpu("27b", dtype, u0, c, arr, 6, algo="mwd")
+            assert_bitwise(got, oracle_run("27b", u0, c, arr, 6, dtype), "box thin %s %s" % (dtype, n))
+    rng = np.random.default_rng(27)
+    for case in range(24):
+        dtype = ("f64", "f32")[case % 2]
+        dw = 8 if dtype == "f64" else (8, 12)[(case // 2) % 2]
+        n = (int(rng.integers(1, 200)), int(rng.integers(1, 50)), int(rng.integers(1, 24)))
+        T = int(rng.integers(0, 3 * dw))
+        print("mwd box random", case, dtype, dw, n, T, flush=True)
+        u0, c, arr = inputs("27b", *n, seed=100 + case)
+        got, _ = run_gpu("27b", dtype, u0, c, arr, T, algo="mwd", params=mwd_params(dw, 1, 2))
+        assert_bitwise(got, oracle_run("27b", u0, c, arr, T, dtype), "box random %d" % case)
 
 
 def test_mwd_random_shapes_match_naive():

@@ -142,17 +142,28 @@ def test_candidates_cover_compiled_variants():
 
 def test_box_plans():
     """The 27-point box stencil: a naive plan streams the field pair (16 B per
-    update in FP64) with the cached variant by default; the plane-tile
-    variant and the blocked algorithm are refused."""
+    update in FP64) with the cached variant by default, and the plane-tile
+    variant is refused; the blocked plan takes Dw = 8 (FP32 also offers
+    Dw = 12), row launches only, with three-plane stage rows."""
     g = G.make_grid(64, 48, 40, 1)
     c = (0.2, 0.05, 0.02, 0.01)
     p = G.girih_plan("27b", "f64", g, c, "naive")
     q, _, bytes_per_lup = G.girih_plan_info(p)
     assert bytes_per_lup == 16.0 and q["variant"] == 0
     G.girih_destroy(p)
-    for algo, params in (("mwd", None), ("naive", {"variant": 1, "threads_x": 64, "threads_y": 8})):
+    with pytest.raises(G.GirihError) as e:
+        G.girih_plan("27b", "f64", g, c, "naive", {"variant": 1, "threads_x": 64, "threads_y": 8})
+    assert e.value.code == G.E_UNSUPPORTED
+    for dt, dws in (("f64", {8}), ("f32", {8, 12})):
+        p = G.girih_plan("27b", dt, g, c, "mwd")
+        q, lds, _ = G.girih_plan_info(p)
+        assert (q["diamond_width"], q["wavefront_depth"], q["variant"]) == (8, 1, 0) and lds <= 160 * 1024
+        cands = G.girih_candidates(p)
+        assert {x["diamond_width"] for x in cands} == dws and {x["variant"] for x in cands} == {0}
+        G.girih_destroy(p)
+    for params in ({"variant": 1}, {"wavefront_depth": 2}, {"diamond_width": 16}):
         with pytest.raises(G.GirihError) as e:
-            G.girih_plan("27b", "f64", g, c, algo, params)
+            G.girih_plan("27b", "f64", g, c, "mwd", params)
         assert e.value.code == G.E_UNSUPPORTED
     with pytest.raises(G.GirihError) as e:
         G.girih_plan("27b", "f64", G.make_grid(64, 48, 40, 2), c, "naive")   # halo != R
