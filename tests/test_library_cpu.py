@@ -143,8 +143,8 @@ def test_candidates_cover_compiled_variants():
 def test_box_plans():
     """The 27-point box stencil: a naive plan streams the field pair (16 B per
     update in FP64) with the cached variant by default, and the plane-tile
-    variant is refused; the blocked plan takes Dw = 8 (FP32 also offers
-    Dw = 12), row launches only, with three-plane stage rows."""
+    variant is refused; the blocked plan takes Dw = 8 in FP64 and 12 in FP32
+    (which also offers 8), row launches only, with three-plane stage rows."""
     g = G.make_grid(64, 48, 40, 1)
     c = (0.2, 0.05, 0.02, 0.01)
     p = G.girih_plan("27b", "f64", g, c, "naive")
@@ -154,10 +154,10 @@ def test_box_plans():
     with pytest.raises(G.GirihError) as e:
         G.girih_plan("27b", "f64", g, c, "naive", {"variant": 1, "threads_x": 64, "threads_y": 8})
     assert e.value.code == G.E_UNSUPPORTED
-    for dt, dws in (("f64", {8}), ("f32", {8, 12})):
+    for dt, dws, dflt in (("f64", {8}, 8), ("f32", {8, 12}, 12)):
         p = G.girih_plan("27b", dt, g, c, "mwd")
         q, lds, _ = G.girih_plan_info(p)
-        assert (q["diamond_width"], q["wavefront_depth"], q["variant"]) == (8, 1, 0) and lds <= 160 * 1024
+        assert (q["diamond_width"], q["wavefront_depth"], q["variant"]) == (dflt, 1, 0) and lds <= 160 * 1024
         cands = G.girih_candidates(p)
         assert {x["diamond_width"] for x in cands} == dws and {x["variant"] for x in cands} == {0}
         G.girih_destroy(p)
