@@ -120,12 +120,21 @@ typedef struct girih_grid {
  *  NAIVE: variant        0 = x/y neighbours through the caches (any block
  *                        of at most 256 threads, threads_x a multiple of 64),
  *                        1 = each plane's x/y neighbourhood staged in an LDS
- *                        tile (threads_x = 64, threads_y = 4, 8 or 16);
+ *                        tile (threads_x = 64, threads_y = 4, 8 or 16); for
+ *                        GIRIH_27PT_BOX, 1 = register columns: each wave of
+ *                        64 lanes holds cells_per_lane (2, 4 or 8) rows along
+ *                        y of three planes, takes x neighbours from the
+ *                        neighbouring lanes and stores 62 x cells per row
+ *                        (threads_x = 64, threads_y = 2 or 4; tile_x and
+ *                        tile_y are filled in: 62 and threads_y *
+ *                        cells_per_lane);
  *         threads_x, threads_y  block shape (x lanes, y rows);
  *         tile_z         z planes each thread marches.
  *         All zero: variant 1 with 64 x 16 threads and z chunks of up to
  *         128 planes; for the 7-point constant stencil in FP32 variant 0
- *         with 64 x 4 threads and up to 64 planes; fewer planes per chunk on
+ *         with 64 x 4 threads and up to 64 planes; for the box stencil
+ *         variant 1 with 64 x 2 threads of 8 rows and up to 32 planes (FP64)
+ *         or of 4 rows and up to 12 planes (FP32); fewer planes per chunk on
  *         small grids. */
 typedef struct girih_params {
     int32_t diamond_width;

@@ -78,13 +78,33 @@ hipError_t launch_naive_box(const void* args, dim3 grid, dim3 block, hipStream_t
     return hipGetLastError();
 }
 
-// The 27-point box stencil: the cached naive sweep (variant 0) and the
-// blocked sweep with its three-plane stage rows (one CU holds them at Dw = 8
-// in FP64, 159 of 160 KiB, and up to Dw = 12 in FP32).
+template <typename Real, int KY>
+hipError_t launch_naive_box_cols(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
+    hipLaunchKernelGGL((naive_box_cols_kernel<Real, KY>), grid, block, 0, stream,
+                       *static_cast<const NaiveArgs<Real>*>(args));
+    return hipGetLastError();
+}
+
+// register columns: blocks of 64 x W threads, KY rows per lane (vx = KY)
+template <typename Real, int KY>
+void add_box_cols(std::vector<KernelEntry>& t, int st, int dt) {
+    for (int w : {2, 4})
+        t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, KY, 0, 64 * w, 0, 0, 0, 1, 0,
+                                reinterpret_cast<const void*>(&naive_box_cols_kernel<Real, KY>),
+                                &launch_naive_box_cols<Real, KY>});
+}
+
+// The 27-point box stencil: the naive sweep with cached neighbours (variant
+// 0) or register columns (variant 1), and the blocked sweep with its
+// three-plane stage rows (one CU holds them at Dw = 8 in FP64, 159 of 160
+// KiB, and up to Dw = 12 in FP32).
 template <typename Real>
 void add_box_family(std::vector<KernelEntry>& t, int st, int dt) {
     t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0, 0,
                             reinterpret_cast<const void*>(&naive_box_kernel<Real>), &launch_naive_box<Real>});
+    add_box_cols<Real, 2>(t, st, dt);
+    add_box_cols<Real, 4>(t, st, dt);
+    add_box_cols<Real, 8>(t, st, dt);
     add_mwd<Stencil27B, Real, 8, 1, 2, 1, false, 0>(t, st, dt);
     if constexpr (sizeof(Real) == 4) add_mwd<Stencil27B, Real, 12, 1, 2, 1, false, 0>(t, st, dt);
 }

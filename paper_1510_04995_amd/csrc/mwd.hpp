@@ -65,6 +65,7 @@
 #pragma once
 #include <type_traits>
 
+#include "lanes.hpp"
 #include "stencils.hpp"
 
 namespace girih {
@@ -91,21 +92,6 @@ __device__ __forceinline__ int64_t opaque_s(int64_t v) {
     int lo = opaque_s((int)(uint32_t)(uint64_t)v);
     int hi = opaque_s((int)(uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
-}
-
-// Value of a neighbouring lane of the wave (DPP move; CTRL 0x130 = wave_shl:1,
-// lane i takes lane i+1; 0x138 = wave_shr:1, lane i takes lane i-1); a lane
-// with no source lane gets zero (bound_ctrl).
-template <int CTRL, typename Real>
-__device__ __forceinline__ Real lane_shift(Real v) {
-    if constexpr (sizeof(Real) == 8) {
-        const uint64_t b = __builtin_bit_cast(uint64_t, v);
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, true);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, true);
-        return __builtin_bit_cast(Real, ((uint64_t)hi << 32) | lo);
-    } else {
-        return __builtin_bit_cast(Real, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
-    }
 }
 
 template <typename Real>

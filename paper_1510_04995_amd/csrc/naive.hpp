@@ -10,6 +10,7 @@
 // the L1/L2 caches.  x is the fastest index, so every access is a contiguous
 // x-row of the wave.
 #pragma once
+#include "lanes.hpp"
 #include "stencils.hpp"
 
 namespace girih {
@@ -111,6 +112,98 @@ naive_box_kernel(NaiveArgs<Real> a) {
             w[0][c] = w[1][c];
             w[1][c] = w[2][c];
         }
+    }
+}
+
+// Box stencil, variant 1: register columns, no LDS and no barriers.  A wave
+// holds 64 consecutive x cells (x0 - 1 .. x0 + 62) of KY + 2 rows along y
+// (y0 - 1 .. y0 + KY) for the planes z - 1, z, z + 1, and marches z over its
+// chunk reading one new plane (KY + 2 coalesced rows) per step, one step
+// ahead.  The x - 1 and x + 1 values of a new plane come from the
+// neighbouring lanes (two DPP moves per row) and are kept with it, so an
+// update reads all 27 operands from registers.  Lanes 0 and 63 only load
+// (their outer neighbour is in no register): each wave stores 62 x cells of
+// KY rows.  Blocks are 64 x W threads; the grid is ceil(nx / 62) x
+// ceil(ny / (W KY)) x z chunks, renumbered into XCD-contiguous runs as in the
+// plane-tile kernel (the y halo rows of a block are its neighbours' rows).
+template <typename Real, int KY>
+__global__ void __launch_bounds__(256)
+naive_box_cols_kernel(NaiveArgs<Real> a) {
+    constexpr int NR = KY + 2;   // rows a lane holds per plane
+    const GridDesc& g = a.g;
+    const int lane = (int)threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const uint32_t NXCD = a.xcd_runs ? 8u : 1u;
+    const uint32_t gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+    const uint32_t lid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t per_xcd = nb / NXCD, extra = nb % NXCD, xcd = lid % NXCD, pos = lid / NXCD;
+    const uint32_t tid_run = (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
+    const uint32_t bx = tid_run % gx, by = (tid_run / gx) % gy, bz = tid_run / (gx * gy);
+    const int64_t y0 = ((int64_t)by * blockDim.y + wave) * KY;
+    const int64_t z0 = (int64_t)bz * a.z_chunk;
+    int64_t z1 = z0 + a.z_chunk;
+    if (z1 > g.nz) z1 = g.nz;
+    // both conditions are uniform across the wave, and nothing below waits
+    // on other waves
+    if (y0 >= g.ny || z0 >= z1) return;
+    const int64_t x = (int64_t)bx * 62 + lane - 1;
+    // rows and columns clamped into the haloed box (cells past it belong to
+    // no stored neighbourhood)
+    const int64_t xc = x < -1 ? -1 : (x > g.nx ? g.nx : x);
+    const bool st_x = lane >= 1 && lane <= 62 && x < g.nx;
+    const int64_t plane = g.plane();
+    int64_t ro[NR];   // element offset of row y0 - 1 + r, column xc, in plane -h
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int64_t yr = y0 - 1 + r > g.ny ? g.ny : y0 - 1 + r;
+        ro[r] = g.idx(-g.h, yr, xc);
+    }
+    const Real* __restrict__ V = a.V;
+    Real* __restrict__ U = a.U;
+    // planes z - 1, z, z + 1 at ring slots (ph, ph + 1, ph + 2) mod 3: the
+    // lane's own value (c) and those of x - 1 (l) and x + 1 (r)
+    Real c[3][NR], l[3][NR], r[3][NR], nxt[NR];
+    auto load = [&](Real (&d)[NR], int64_t q) __attribute__((always_inline)) {
+        const int64_t off = (q + g.h) * plane;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) d[k] = V[off + ro[k]];
+    };
+    auto insert = [&](int s, const Real (&v)[NR]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            c[s][k] = v[k];
+            l[s][k] = lane_shift<0x138>(v[k]);
+            r[s][k] = lane_shift<0x130>(v[k]);
+        }
+    };
+    load(nxt, z0 - 1);
+    insert(0, nxt);
+    load(nxt, z0);
+    insert(1, nxt);
+    load(nxt, z0 + 1);
+    auto step = [&](auto phc, int64_t z) __attribute__((always_inline)) {
+        constexpr int ph = decltype(phc)::value;
+        constexpr int s2 = (ph + 2) % 3;
+        insert(s2, nxt);
+        if (z + 1 < z1) load(nxt, z + 2);   // plane z + 2 <= nz: inside the haloed box
+        const int64_t off = (z + g.h) * plane;
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            Box27<Real> b;
+#pragma unroll
+            for (int m = 0; m < 27; ++m) {
+                const int dz = m / 9 - 1, dy = (m / 3) % 3 - 1, dx = m % 3 - 1;
+                const int s = (ph + 1 + dz + 3) % 3, row = k + 1 + dy;
+                b.v[m] = dx < 0 ? l[s][row] : (dx > 0 ? r[s][row] : c[s][row]);
+            }
+            const Real u = Stencil27B::apply_box(b, a.coef.k);
+            if (st_x && y0 + k < g.ny) U[off + ro[k + 1]] = u;
+        }
+    };
+    for (int64_t z = z0; z < z1; z += 3) {
+        step(std::integral_constant<int, 0>{}, z);
+        if (z + 1 < z1) step(std::integral_constant<int, 1>{}, z + 1);
+        if (z + 2 < z1) step(std::integral_constant<int, 2>{}, z + 2);
     }
 }
 

@@ -165,10 +165,12 @@ const KernelEntry* mwd_kernel_for(const KernelEntry* full, int need) {
 
 // Naive kernel: variant 0 takes any block shape; variant 1 (plane tiles in
 // LDS) exists for blocks of 64 x `rows` threads.
-const KernelEntry* find_naive(int st, int dt, int variant, int rows) {
+// For the box stencil variant 1 is register columns, for blocks of 64 x
+// `rows` threads holding `cells` y rows per lane.
+const KernelEntry* find_naive(int st, int dt, int variant, int rows, int cells) {
     for (const auto& e : kernel_table())
         if (e.algo == AL_NAIVE && e.stencil == st && e.dtype == dt && e.variant == variant &&
-            (variant == 0 || e.nthreads == 64 * rows))
+            (variant == 0 || e.nthreads == 64 * rows) && (e.vx == 0 || e.vx == cells))
             return &e;
     return nullptr;
 }
@@ -295,16 +297,26 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         // plane cost more there than the halo re-reads).  The z chunk keeps
         // at least two blocks per CU on small grids.
         const bool dflt = !in || (in->threads_x == 0 && in->threads_y == 0 && in->variant == 0);
+        const bool box = p->stencil == GIRIH_27PT_BOX;
         if (dflt) {
-            // (the box stencil has the cached variant only)
-            const bool cached = (p->stencil == GIRIH_7PT_CONST && p->dtype == GIRIH_F32) || p->stencil == GIRIH_27PT_BOX;
+            const bool cached = p->stencil == GIRIH_7PT_CONST && p->dtype == GIRIH_F32;
             q.threads_x = 64;
             q.threads_y = cached ? 4 : 16;
             q.variant = cached ? 0 : 1;
+            if (box) {
+                // register columns (512^3: 1.6x the cached variant in FP64,
+                // 1.5x in FP32): 2 waves per block of 8 rows (FP64) or 4 rows
+                // (FP32), in z chunks of up to 32 (FP64) or 12 (FP32) planes
+                q.threads_y = 2;
+                if (q.cells_per_lane == 0) q.cells_per_lane = p->dtype == GIRIH_F64 ? 8 : 4;
+            }
             if (q.tile_z == 0) {
-                const int64_t cols = ((p->grid.nx + 63) / 64) * ((p->grid.ny + q.threads_y - 1) / q.threads_y);
+                // columns of blocks (register columns: of waves)
+                const int64_t cols = box ? ((p->grid.nx + 61) / 62) * ((p->grid.ny + q.cells_per_lane - 1) / q.cells_per_lane)
+                                         : ((p->grid.nx + 63) / 64) * ((p->grid.ny + q.threads_y - 1) / q.threads_y);
                 const int64_t tz = cols * p->grid.nz / 512;
-                q.tile_z = (int32_t)std::max<int64_t>(8, std::min<int64_t>(cached ? 64 : 128, tz));
+                const int64_t cap = box ? (p->dtype == GIRIH_F64 ? 32 : 12) : cached ? 64 : 128;
+                q.tile_z = (int32_t)std::max<int64_t>(std::min<int64_t>(8, cap), std::min<int64_t>(cap, tz));
             }
         }
         if (q.threads_x == 0) q.threads_x = 64;
@@ -314,13 +326,17 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         if (q.variant != 0 && q.variant != 1) return GIRIH_E_UNSUPPORTED;
         if (q.variant == 0 && (q.threads_x * q.threads_y > 256 || q.threads_x % 64)) return GIRIH_E_INVALID;
         if (q.variant == 1 && q.threads_x != 64) return GIRIH_E_INVALID;
-        p->kern = find_naive(p->stencil, p->dtype, q.variant, q.threads_y);
+        const bool cols = box && q.variant == 1;   // register columns
+        if (cols && q.cells_per_lane == 0) q.cells_per_lane = 4;
+        p->kern = find_naive(p->stencil, p->dtype, q.variant, q.threads_y, cols ? q.cells_per_lane : 0);
         if (!p->kern) return GIRIH_E_UNSUPPORTED;
         q.diamond_width = 0;
         q.wavefront_depth = 0;
-        q.tile_x = q.threads_x;
-        q.tile_y = q.threads_y;
-        q.cells_per_lane = 1;
+        // x and y cells a block stores (register columns: 62 lanes of each
+        // wave, cells_per_lane rows per lane)
+        q.tile_x = cols ? 62 : q.threads_x;
+        q.tile_y = cols ? q.threads_y * q.cells_per_lane : q.threads_y;
+        if (!cols) q.cells_per_lane = 1;
     }
     p->params = q;
     return GIRIH_OK;
@@ -378,7 +394,8 @@ int run_naive(girih_plan_s* p, void* buf0, void* buf1, const void* const* coefs,
     // domain-sized streams of 25v (-16 %)
     a.xcd_runs = kStreams[p->stencil] <= 9 ? 1 : 0;
     const dim3 block(p->params.threads_x, p->params.threads_y);
-    const dim3 grid((unsigned)((p->grid.nx + block.x - 1) / block.x), (unsigned)((p->grid.ny + block.y - 1) / block.y),
+    const int64_t bx = p->params.tile_x, by = p->params.tile_y;   // cells a block stores along x and y
+    const dim3 grid((unsigned)((p->grid.nx + bx - 1) / bx), (unsigned)((p->grid.ny + by - 1) / by),
                     (unsigned)((p->grid.nz + a.z_chunk - 1) / a.z_chunk));
     Real* b[2] = {static_cast<Real*>(buf0), static_cast<Real*>(buf1)};
     for (int64_t t = 0; t < T; ++t) {

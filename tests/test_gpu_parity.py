@@ -70,6 +70,38 @@ def test_box_block_shapes_halo_and_pitch():
         assert_bitwise(got, ref, "box padded %s" % dtype)
 
 
+def test_box_register_columns():
+    """The box stencil's register-column sweep (variant 1) in every compiled
+    shape (2 or 4 waves, 2, 4 or 8 rows per lane), with z chunks that do and
+    do not divide nz, a nonzero halo with a -0.0, padded pitches, and grids
+    whose x extent falls on, just below and just above the 62 cells a wave
+    stores, bit for bit against the oracle."""
+    u0, c, arr = inputs("27b", 70, 33, 41, seed=4)
+    rng = np.random.default_rng(4)
+    halo = np.ones(u0.shape, bool)
+    halo[1:-1, 1:-1, 1:-1] = False
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    u0[0, 0, 0] = -0.0
+    for dtype in ("f64", "f32"):
+        ref = oracle_run("27b", u0, c, arr, 4, dtype)
+        for w in (2, 4):
+            for ky in (2, 4, 8):
+                for tz in (7, 41, 200):
+                    p = {"variant": 1, "threads_x": 64, "threads_y": w, "cells_per_lane": ky, "tile_z": tz}
+                    print("box columns", dtype, p, flush=True)
+                    got, info = run_gpu("27b", dtype, u0, c, arr, 4, algo="naive", params=p)
+                    assert (info["params"]["tile_y"], info["params"]["cells_per_lane"]) == (w * ky, ky)
+                    assert_bitwise(got, ref, "box columns %s %s" % (dtype, p))
+        got, _ = run_gpu("27b", dtype, u0, c, arr, 4, algo="naive", pitch=(80, 40))
+        assert_bitwise(got, ref, "box columns padded %s" % dtype)
+    for n in ((61, 5, 9), (62, 16, 3), (63, 17, 4), (1, 1, 1), (130, 47, 12), (124, 1, 2), (2, 70, 5)):
+        u0, c, arr = inputs("27b", *n, seed=5)
+        for dtype in ("f64", "f32"):
+            print("box columns grid", dtype, n, flush=True)
+            got, _ = run_gpu("27b", dtype, u0, c, arr, 5, algo="naive")
+            assert_bitwise(got, oracle_run("27b", u0, c, arr, 5, dtype), "box columns %s %s" % (dtype, n))
+
+
 @pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v", "25l"])
 def test_naive_plane_tiles_bitwise(stencil):
     """The LDS-tile naive sweep (variant 1) at every compiled tile height, on

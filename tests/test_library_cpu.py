@@ -142,18 +142,35 @@ def test_candidates_cover_compiled_variants():
 
 def test_box_plans():
     """The 27-point box stencil: a naive plan streams the field pair (16 B per
-    update in FP64) with the cached variant by default, and the plane-tile
-    variant is refused; the blocked plan takes Dw = 8 in FP64 and 12 in FP32
-    (which also offers 8), row launches only, with three-plane stage rows."""
+    update in FP64) with register columns by default (variant 1: 62 x cells
+    per wave, in FP64 8 rows per lane and 64 x 2 threads), and the cached
+    variant on request;
+    blocks wider than 256 threads or rows per lane not compiled are refused.
+    The blocked plan takes Dw = 8 in FP64 and 12 in FP32 (which also offers
+    8), row launches only, with three-plane stage rows."""
     g = G.make_grid(64, 48, 40, 1)
     c = (0.2, 0.05, 0.02, 0.01)
     p = G.girih_plan("27b", "f64", g, c, "naive")
-    q, _, bytes_per_lup = G.girih_plan_info(p)
-    assert bytes_per_lup == 16.0 and q["variant"] == 0
+    q, lds, bytes_per_lup = G.girih_plan_info(p)
+    assert bytes_per_lup == 16.0 and lds == 0
+    assert (q["variant"], q["threads_x"], q["threads_y"], q["cells_per_lane"], q["tile_x"], q["tile_y"]) == \
+        (1, 64, 2, 8, 62, 16)
     G.girih_destroy(p)
-    with pytest.raises(G.GirihError) as e:
-        G.girih_plan("27b", "f64", g, c, "naive", {"variant": 1, "threads_x": 64, "threads_y": 8})
-    assert e.value.code == G.E_UNSUPPORTED
+    for params, want in (({"variant": 0, "threads_x": 64, "threads_y": 4}, (0, 64, 4, 1)),
+                         ({"variant": 1, "threads_x": 64, "threads_y": 2, "cells_per_lane": 8}, (62, 16, 2, 8)),
+                         ({"variant": 1, "threads_x": 64, "threads_y": 4, "cells_per_lane": 2}, (62, 8, 4, 2))):
+        p = G.girih_plan("27b", "f32", g, c, "naive", params)
+        q, _, _ = G.girih_plan_info(p)
+        if params["variant"] == 0:
+            assert (q["variant"], q["threads_x"], q["threads_y"], q["cells_per_lane"]) == want
+        else:
+            assert (q["tile_x"], q["tile_y"], q["threads_y"], q["cells_per_lane"]) == want
+        G.girih_destroy(p)
+    for params in ({"variant": 1, "threads_x": 64, "threads_y": 8}, {"variant": 1, "threads_x": 64, "threads_y": 4,
+                                                                     "cells_per_lane": 3}):
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan("27b", "f64", g, c, "naive", params)
+        assert e.value.code == G.E_UNSUPPORTED
     for dt, dws, dflt in (("f64", {8}, 8), ("f32", {8, 12}, 12)):
         p = G.girih_plan("27b", dt, g, c, "mwd")
         q, lds, _ = G.girih_plan_info(p)
