@@ -127,15 +127,22 @@ typedef struct girih_grid {
  *                        neighbouring lanes and stores 62 x cells per row
  *                        (threads_x = 64, threads_y = 2 or 4; tile_x and
  *                        tile_y are filled in: 62 and threads_y *
- *                        cells_per_lane);
+ *                        cells_per_lane),
+ *                        2 = register columns for GIRIH_7PT_CONST and
+ *                        GIRIH_25PT_CONST: each wave holds cells_per_lane
+ *                        (2, 4 or 8) rows of the 2R+1 planes of their
+ *                        z-window and the 2R rows beside them, takes x
+ *                        neighbours from the neighbouring lanes and stores
+ *                        64 - 2R x cells per row (same block shapes; tile_x
+ *                        = 64 - 2R);
  *         threads_x, threads_y  block shape (x lanes, y rows);
  *         tile_z         z planes each thread marches.
  *         All zero: variant 1 with 64 x 16 threads and z chunks of up to
- *         128 planes; for the 7-point constant stencil in FP32 variant 0
- *         with 64 x 4 threads and up to 64 planes; for the box stencil
- *         variant 1 with 64 x 2 threads of 8 rows and up to 32 planes (FP64)
- *         or of 4 rows and up to 12 planes (FP32); fewer planes per chunk on
- *         small grids. */
+ *         128 planes; in FP32 for GIRIH_7PT_CONST and GIRIH_25PT_CONST
+ *         variant 2 with 64 x 2 threads of 4 and 8 rows and up to 12 planes;
+ *         for the box stencil variant 1 with 64 x 2 threads of 8 rows and up
+ *         to 32 planes (FP64) or of 4 rows and up to 12 planes (FP32); fewer
+ *         planes per chunk on small grids. */
 typedef struct girih_params {
     int32_t diamond_width;
     int32_t wavefront_depth;

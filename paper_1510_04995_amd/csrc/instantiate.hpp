@@ -109,6 +109,22 @@ void add_box_family(std::vector<KernelEntry>& t, int st, int dt) {
     if constexpr (sizeof(Real) == 4) add_mwd<Stencil27B, Real, 12, 1, 2, 1, false, 0>(t, st, dt);
 }
 
+template <class S, typename Real, int KY>
+hipError_t launch_naive_star_cols(const void* args, dim3 grid, dim3 block, hipStream_t stream) {
+    hipLaunchKernelGGL((naive_star_cols_kernel<S, Real, KY>), grid, block, 0, stream,
+                       *static_cast<const NaiveArgs<Real>*>(args));
+    return hipGetLastError();
+}
+
+// register columns (variant 2): blocks of 64 x W threads, KY rows per lane (vx = KY)
+template <class S, typename Real, int KY>
+void add_star_cols(std::vector<KernelEntry>& t, int st, int dt) {
+    for (int w : {2, 4})
+        t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, KY, 0, 64 * w, 0, 0, 0, 2, 0,
+                                reinterpret_cast<const void*>(&naive_star_cols_kernel<S, Real, KY>),
+                                &launch_naive_star_cols<S, Real, KY>});
+}
+
 template <class S, typename Real>
 void add_naive(std::vector<KernelEntry>& t, int st, int dt) {
     t.push_back(KernelEntry{st, dt, AL_NAIVE, 0, 0, 0, 256, 0, 0, 0, 0, 0,
@@ -117,6 +133,11 @@ void add_naive(std::vector<KernelEntry>& t, int st, int dt) {
     add_naive_tile<S, Real, 4>(t, st, dt);
     add_naive_tile<S, Real, 8>(t, st, dt);
     add_naive_tile<S, Real, 16>(t, st, dt);
+    if constexpr (S::NCOEF == 0 && !S::LEAPFROG) {
+        add_star_cols<S, Real, 2>(t, st, dt);
+        add_star_cols<S, Real, 4>(t, st, dt);
+        add_star_cols<S, Real, 8>(t, st, dt);
+    }
 }
 
 // Variants per radius and element size.  Each keeps its z-rings in registers

@@ -10,10 +10,21 @@
 // the L1/L2 caches.  x is the fastest index, so every access is a contiguous
 // x-row of the wave.
 #pragma once
+#include <type_traits>
+
 #include "lanes.hpp"
 #include "stencils.hpp"
 
 namespace girih {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B..E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_n(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for_n<B + 1, E>(f);
+    }
+}
 
 template <typename Real>
 struct NaiveArgs {
@@ -152,7 +163,11 @@ naive_box_cols_kernel(NaiveArgs<Real> a) {
     const int64_t xc = x < -1 ? -1 : (x > g.nx ? g.nx : x);
     const bool st_x = lane >= 1 && lane <= 62 && x < g.nx;
     const int64_t plane = g.plane();
-    int64_t ro[NR];   // element offset of row y0 - 1 + r, column xc, in plane -h
+    // per-lane element offsets of the rows (row y0 - 1 + r clamped to the
+    // halo row ny) in plane -h: kept in registers across the sweep, which
+    // measured faster here than a wave-uniform row offset plus a lane offset
+    // recomputed at every access (278 against 242 GLUP/s in FP64)
+    int64_t ro[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int64_t yr = y0 - 1 + r > g.ny ? g.ny : y0 - 1 + r;
@@ -204,6 +219,116 @@ naive_box_cols_kernel(NaiveArgs<Real> a) {
         step(std::integral_constant<int, 0>{}, z);
         if (z + 1 < z1) step(std::integral_constant<int, 1>{}, z + 1);
         if (z + 2 < z1) step(std::integral_constant<int, 2>{}, z + 2);
+    }
+}
+
+// Star stencils with constant coefficients, variant 2: register columns, no
+// LDS and no barriers.  A wave holds 64 consecutive x cells (x0 - R ..
+// x0 + 63 - R) of KY rows (y0 .. y0 + KY - 1) for the 2R + 1 planes of their
+// z-window, and the 2R rows beside them (y0 - R .. y0 - 1, y0 + KY ..
+// y0 + KY + R - 1) of the centre plane.  Per z step it loads one new plane of
+// its rows and the side rows of the next centre plane, both one step ahead;
+// the x neighbours are the neighbouring lanes' centre values (r chained DPP
+// moves reach x + r), so lanes 0 .. R-1 and 64-R .. 63 only load and each
+// wave stores 64 - 2R x cells of KY rows.  Blocks are 64 x W threads on a
+// grid of ceil(nx / (64 - 2R)) x ceil(ny / (W KY)) x z chunks, numbered in
+// XCD-contiguous runs.
+template <class S, typename Real, int KY>
+__global__ void __launch_bounds__(256)
+naive_star_cols_kernel(NaiveArgs<Real> a) {
+    constexpr int R = S::R, NZ = 2 * R + 1, OWN = 64 - 2 * R;
+    static_assert(S::NCOEF == 0 && !S::LEAPFROG && !S::BOX, "constant-coefficient star stencils");
+    const GridDesc& g = a.g;
+    const int lane = (int)threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const uint32_t NXCD = a.xcd_runs ? 8u : 1u;
+    const uint32_t gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+    const uint32_t lid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t per_xcd = nb / NXCD, extra = nb % NXCD, xcd = lid % NXCD, pos = lid / NXCD;
+    const uint32_t tid_run = (xcd < extra ? xcd * (per_xcd + 1) : extra * (per_xcd + 1) + (xcd - extra) * per_xcd) + pos;
+    const uint32_t bx = tid_run % gx, by = (tid_run / gx) % gy, bz = tid_run / (gx * gy);
+    const int64_t y0 = ((int64_t)by * blockDim.y + wave) * KY;
+    const int64_t z0 = (int64_t)bz * a.z_chunk;
+    int64_t z1 = z0 + a.z_chunk;
+    if (z1 > g.nz) z1 = g.nz;
+    // uniform across the wave; nothing below waits on other waves
+    if (y0 >= g.ny || z0 >= z1) return;
+    const int64_t x = (int64_t)bx * OWN + lane - R;
+    // rows and columns clamped into the haloed box (cells past it belong to
+    // no stored neighbourhood)
+    const int64_t xc = x >= g.nx + R ? g.nx + R - 1 : x;   // x >= -R always
+    const bool st_x = lane >= R && lane < 64 - R && x < g.nx;
+    auto clampy = [&](int64_t y) { return y < -R ? -R : (y > g.ny + R - 1 ? g.ny + R - 1 : y); };
+    const int64_t plane = g.plane();
+    // addresses: a row's element offset (uniform across the wave, so held in
+    // scalar registers) plus the lane's byte offset within the row
+    const uint32_t xb = (uint32_t)((xc + g.h) * (int64_t)sizeof(Real));
+    auto row_off = [&](int64_t y) { return (clampy(y) + g.h) * g.pitch_x; };
+    auto at = [&](const Real* base) -> const Real& {
+        return *reinterpret_cast<const Real*>(reinterpret_cast<const char*>(base) + xb);
+    };
+    const Real* __restrict__ V = a.V;
+    Real* __restrict__ U = a.U;
+    // z-window of the own rows: plane z + d at slot (ph + R + d) mod NZ
+    Real w[NZ][KY], nxt[KY], side[2 * R], snx[2 * R];
+    auto load_rows = [&](Real (&d)[KY], int64_t q) __attribute__((always_inline)) {
+        const Real* pb = V + (q + g.h) * plane;
+#pragma unroll
+        for (int k = 0; k < KY; ++k) d[k] = at(pb + row_off(y0 + k));
+    };
+    // side rows y0 - R .. y0 - 1 (index i < R) and y0 + KY .. y0 + KY + R - 1
+    auto load_side = [&](Real (&d)[2 * R], int64_t q) __attribute__((always_inline)) {
+        const Real* pb = V + (q + g.h) * plane;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            d[i] = at(pb + row_off(y0 - R + i));
+            d[R + i] = at(pb + row_off(y0 + KY + i));
+        }
+    };
+    // planes z0 - R .. z0 + R - 1 (inside the haloed box: z0 >= 0, z0 + R - 1 < nz + R)
+    static_for_n<0, 2 * R>([&](auto dc) __attribute__((always_inline)) {
+        constexpr int d = decltype(dc)::value;
+        load_rows(w[d], z0 - R + d);
+    });
+    load_rows(nxt, z0 + R);
+    load_side(snx, z0);
+    auto step = [&](auto phc, int64_t z) __attribute__((always_inline)) {
+        constexpr int ph = decltype(phc)::value;
+        // plane z + R enters the window; the side rows of plane z become current
+#pragma unroll
+        for (int k = 0; k < KY; ++k) w[(ph + 2 * R) % NZ][k] = nxt[k];
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) side[i] = snx[i];
+        if (z + 1 < z1) {
+            load_rows(nxt, z + 1 + R);   // <= z1 - 1 + R < nz + R
+            load_side(snx, z + 1);
+        }
+        Real* const ub = U + (z + g.h) * plane;
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            Nbhd<Real, R> n;
+            n.c = w[(ph + R) % NZ][k];
+            Real xp = n.c, xm = n.c;
+#pragma unroll
+            for (int r = 1; r <= R; ++r) {
+                xp = lane_shift<0x130>(xp);
+                xm = lane_shift<0x138>(xm);
+                n.xp[r - 1] = xp;
+                n.xm[r - 1] = xm;
+                n.zp[r - 1] = w[(ph + R + r) % NZ][k];
+                n.zm[r - 1] = w[(ph + R - r) % NZ][k];
+                n.yp[r - 1] = k + r < KY ? w[(ph + R) % NZ][k + r] : side[R + k + r - KY];
+                n.ym[r - 1] = k - r >= 0 ? w[(ph + R) % NZ][k - r] : side[R + k - r];
+            }
+            const Real u = S::apply(n, a.coef.k, static_cast<const Real*>(nullptr));
+            if (st_x && y0 + k < g.ny)
+                *reinterpret_cast<Real*>(reinterpret_cast<char*>(ub + row_off(y0 + k)) + xb) = u;
+        }
+    };
+    for (int64_t z = z0; z < z1; z += NZ) {
+        static_for_n<0, NZ>([&](auto phc) __attribute__((always_inline)) {
+            if (z + decltype(phc)::value < z1) step(phc, z + decltype(phc)::value);
+        });
     }
 }
 

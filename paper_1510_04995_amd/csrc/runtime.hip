@@ -291,31 +291,42 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         q.threads_y = dw / 2;
     } else {
         // Defaults (measured on the 512^3, 384^3 and 256x512x1024 workloads):
-        // plane tiles in LDS of 64 x 16 cells marching up to 128 planes; for
-        // the 7-point constant stencil in FP32, whose update is the cheapest,
-        // cached neighbours with 64 x 4 blocks (the tile's two barriers per
-        // plane cost more there than the halo re-reads).  The z chunk keeps
-        // at least two blocks per CU on small grids.
+        // plane tiles in LDS of 64 x 16 cells marching up to 128 planes;
+        // register columns for the box stencil (1.6x the cached variant in
+        // FP64, 1.5x in FP32) and, in FP32, for the constant-coefficient star
+        // stencils (7-point 1.3x the cached variant, 25-point 1.26x the plane
+        // tiles; in FP64 they tie or lose).  The z chunk keeps at least two
+        // blocks per CU on small grids.
         const bool dflt = !in || (in->threads_x == 0 && in->threads_y == 0 && in->variant == 0);
         const bool box = p->stencil == GIRIH_27PT_BOX;
         if (dflt) {
-            const bool cached = p->stencil == GIRIH_7PT_CONST && p->dtype == GIRIH_F32;
+            const bool f32 = p->dtype == GIRIH_F32;
+            const bool scols = f32 && (p->stencil == GIRIH_7PT_CONST || p->stencil == GIRIH_25PT_CONST);
             q.threads_x = 64;
-            q.threads_y = cached ? 4 : 16;
-            q.variant = cached ? 0 : 1;
+            q.threads_y = 16;
+            q.variant = 1;
+            int64_t cap = 128;
             if (box) {
-                // register columns (512^3: 1.6x the cached variant in FP64,
-                // 1.5x in FP32): 2 waves per block of 8 rows (FP64) or 4 rows
-                // (FP32), in z chunks of up to 32 (FP64) or 12 (FP32) planes
+                // 2 waves per block of 8 rows (FP64) or 4 rows (FP32), z chunks
+                // of up to 32 (FP64) or 12 (FP32) planes
                 q.threads_y = 2;
-                if (q.cells_per_lane == 0) q.cells_per_lane = p->dtype == GIRIH_F64 ? 8 : 4;
+                if (q.cells_per_lane == 0) q.cells_per_lane = f32 ? 4 : 8;
+                cap = f32 ? 12 : 32;
+            } else if (scols) {
+                // 2 waves per block of 4 (7-point) or 8 (25-point) rows, z
+                // chunks of up to 12 planes
+                q.threads_y = 2;
+                q.variant = 2;
+                if (q.cells_per_lane == 0) q.cells_per_lane = p->stencil == GIRIH_7PT_CONST ? 4 : 8;
+                cap = 12;
             }
             if (q.tile_z == 0) {
                 // columns of blocks (register columns: of waves)
-                const int64_t cols = box ? ((p->grid.nx + 61) / 62) * ((p->grid.ny + q.cells_per_lane - 1) / q.cells_per_lane)
+                const int64_t own = 64 - 2 * kRadius[p->stencil];
+                const int64_t cols = box || scols
+                                         ? ((p->grid.nx + own - 1) / own) * ((p->grid.ny + q.cells_per_lane - 1) / q.cells_per_lane)
                                          : ((p->grid.nx + 63) / 64) * ((p->grid.ny + q.threads_y - 1) / q.threads_y);
                 const int64_t tz = cols * p->grid.nz / 512;
-                const int64_t cap = box ? (p->dtype == GIRIH_F64 ? 32 : 12) : cached ? 64 : 128;
                 q.tile_z = (int32_t)std::max<int64_t>(std::min<int64_t>(8, cap), std::min<int64_t>(cap, tz));
             }
         }
@@ -323,18 +334,20 @@ int resolve(girih_plan_s* p, const girih_params* in) {
         if (q.threads_y == 0) q.threads_y = 4;
         if (q.tile_z == 0) q.tile_z = 64;
         if (q.threads_x <= 0 || q.threads_y <= 0 || q.tile_z <= 0) return GIRIH_E_INVALID;
-        if (q.variant != 0 && q.variant != 1) return GIRIH_E_UNSUPPORTED;
+        if (q.variant < 0 || q.variant > 2) return GIRIH_E_UNSUPPORTED;
         if (q.variant == 0 && (q.threads_x * q.threads_y > 256 || q.threads_x % 64)) return GIRIH_E_INVALID;
-        if (q.variant == 1 && q.threads_x != 64) return GIRIH_E_INVALID;
-        const bool cols = box && q.variant == 1;   // register columns
+        if (q.variant >= 1 && q.threads_x != 64) return GIRIH_E_INVALID;
+        // register columns: variant 1 of the box stencil, variant 2 of the
+        // constant-coefficient star stencils
+        const bool cols = (box && q.variant == 1) || q.variant == 2;
         if (cols && q.cells_per_lane == 0) q.cells_per_lane = 4;
         p->kern = find_naive(p->stencil, p->dtype, q.variant, q.threads_y, cols ? q.cells_per_lane : 0);
         if (!p->kern) return GIRIH_E_UNSUPPORTED;
         q.diamond_width = 0;
         q.wavefront_depth = 0;
-        // x and y cells a block stores (register columns: 62 lanes of each
-        // wave, cells_per_lane rows per lane)
-        q.tile_x = cols ? 62 : q.threads_x;
+        // x and y cells a block stores (register columns: 64 - 2R lanes of
+        // each wave, cells_per_lane rows per lane)
+        q.tile_x = cols ? 64 - 2 * kRadius[p->stencil] : q.threads_x;
         q.tile_y = cols ? q.threads_y * q.cells_per_lane : q.threads_y;
         if (!cols) q.cells_per_lane = 1;
     }

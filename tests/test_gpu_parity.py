@@ -102,6 +102,46 @@ def test_box_register_columns():
             assert_bitwise(got, oracle_run("27b", u0, c, arr, 5, dtype), "box columns %s %s" % (dtype, n))
 
 
+@pytest.mark.parametrize("stencil", ["7c", "25c"])
+def test_star_register_columns(stencil):
+    """Naive variant 2 (register columns) of the constant-coefficient star
+    stencils in every compiled shape (2 or 4 waves, 2, 4 or 8 rows per lane),
+    z chunks that do and do not divide nz, a nonzero halo with a -0.0,
+    padded pitches, and grids whose extents fall on, below and above the
+    64 - 2R x cells and the rows a wave stores, bit for bit against the
+    oracle."""
+    h = 1 if stencil == "7c" else 4
+    u0, c, arr = inputs(stencil, 70, 33, 41, seed=6)
+    rng = np.random.default_rng(6)
+    halo = np.ones(u0.shape, bool)
+    halo[h:-h, h:-h, h:-h] = False
+    u0[halo] = rng.random(int(halo.sum())) - 0.5
+    u0[0, 0, 0] = -0.0
+    for dtype in ("f64", "f32"):
+        ref = oracle_run(stencil, u0, c, arr, 4, dtype)
+        for w in (2, 4):
+            for ky in (2, 4, 8):
+                for tz in (5, 41):
+                    p = {"variant": 2, "threads_x": 64, "threads_y": w, "cells_per_lane": ky, "tile_z": tz}
+                    print("star columns", stencil, dtype, p, flush=True)
+                    got, info = run_gpu(stencil, dtype, u0, c, arr, 4, algo="naive", params=p)
+                    assert (info["params"]["variant"], info["params"]["tile_x"]) == (2, 64 - 2 * h)
+                    assert_bitwise(got, ref, "star columns %s %s %s" % (stencil, dtype, p))
+        p = {"variant": 2, "threads_x": 64, "threads_y": 4, "cells_per_lane": 4}
+        got, _ = run_gpu(stencil, dtype, u0, c, arr, 4, algo="naive", params=p, pitch=(80 + 2 * h, 40 + 2 * h))
+        assert_bitwise(got, ref, "star columns padded %s %s" % (stencil, dtype))
+    own = 64 - 2 * h
+    for n in ((own - 1, 9, 7), (own, 16, 3), (own + 1, 17, 4), (1, 1, 1), (130, 47, 12), (2, 70, 9), (3, 5, 1)):
+        u0, c, arr = inputs(stencil, *n, seed=7)
+        for dtype in ("f64", "f32"):
+            for ky in (2, 8):
+                p = {"variant": 2, "threads_x": 64, "threads_y": 2, "cells_per_lane": ky}
+                print("star columns grid", stencil, dtype, n, p, flush=True)
+                got, _ = run_gpu(stencil, dtype, u0, c, arr, 5, algo="naive", params=p)
+                assert_bitwise(got, oracle_run(stencil, u0, c, arr, 5, dtype),
+                               "star columns %s %s %s %s" % (stencil, dtype, n, p))
+
+
 @pytest.mark.parametrize("stencil", ["7c", "7v", "25c", "25v", "25l"])
 def test_naive_plane_tiles_bitwise(stencil):
     """The LDS-tile naive sweep (variant 1) at every compiled tile height, on

@@ -187,6 +187,48 @@ def test_box_plans():
     assert e.value.code == G.E_INVALID
 
 
+def test_star_register_column_plans():
+    """Naive variant 2 (register columns) for the constant-coefficient star
+    stencils: tile_x = 64 - 2R cells stored per wave, tile_y = waves x rows
+    per lane; refused for the stencils with coefficient arrays or two time
+    levels, for blocks that are not 64 lanes wide, and for rows per lane not
+    compiled."""
+    for st, dt, r, w, ky in (("7c", "f64", 1, 4, 8), ("7c", "f32", 1, 2, 2), ("25c", "f32", 4, 2, 4),
+                              ("25c", "f64", 4, 4, 2)):
+        g = G.make_grid(100, 50, 30, r)
+        c = (0.4, 0.1) if st == "7c" else (0.2, 0.05, 0.04, 0.03, 0.0133)
+        p = G.girih_plan(st, dt, g, c, "naive", {"variant": 2, "threads_x": 64, "threads_y": w,
+                                                  "cells_per_lane": ky, "tile_z": 9})
+        q, lds, _ = G.girih_plan_info(p)
+        assert (q["variant"], q["tile_x"], q["tile_y"], q["cells_per_lane"], q["tile_z"], lds) == \
+            (2, 64 - 2 * r, w * ky, ky, 9, 0)
+        G.girih_destroy(p)
+    # the FP32 default naive plans of both stencils; FP64 keeps the plane tiles
+    for st, dt, r, want in (("7c", "f32", 1, (2, 2, 4, 62, 12)), ("25c", "f32", 4, (2, 2, 8, 56, 12)),
+                            ("7c", "f64", 1, (1, 16, 1, 64, 128)), ("25c", "f64", 4, (1, 16, 1, 64, 128))):
+        c = (0.4, 0.1) if st == "7c" else (0.2, 0.05, 0.04, 0.03, 0.0133)
+        p = G.girih_plan(st, dt, G.make_grid(512, 512, 512, r), c, "naive")
+        q = G.girih_plan_info(p)[0]
+        assert (q["variant"], q["threads_y"], q["cells_per_lane"], q["tile_x"], q["tile_z"]) == want, (st, dt, q)
+        G.girih_destroy(p)
+    g = G.make_grid(100, 50, 30, 1)
+    for st, params, code in (("7v", {"variant": 2, "threads_x": 64, "threads_y": 4}, G.E_UNSUPPORTED),
+                             ("7c", {"variant": 2, "threads_x": 128, "threads_y": 2}, G.E_INVALID),
+                             ("7c", {"variant": 2, "threads_x": 64, "threads_y": 4, "cells_per_lane": 3},
+                              G.E_UNSUPPORTED),
+                             ("7c", {"variant": 3, "threads_x": 64, "threads_y": 4}, G.E_UNSUPPORTED)):
+        c = (0.4, 0.1) if st == "7c" else None
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan(st, "f64", g, c, "naive", params)
+        assert e.value.code == code, (st, params)
+    g4 = G.make_grid(100, 50, 30, 4)
+    for st in ("25v", "25l"):
+        with pytest.raises(G.GirihError) as e:
+            G.girih_plan(st, "f64", g4, None if st == "25v" else (0.2, 0.05, 0.04, 0.03, 0.0133), "naive",
+                         {"variant": 2, "threads_x": 64, "threads_y": 4})
+        assert e.value.code == G.E_UNSUPPORTED
+
+
 def test_default_schedules():
     """The default plan takes the dependency-driven schedule (variant 1)
     where it measured faster -- 25-point constant and 7-point variable in
