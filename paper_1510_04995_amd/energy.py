@@ -26,8 +26,13 @@ CASES = [
     ("7c", "f32", (512, 512, 512), 64, "mwd"),
     ("25c", "f64", (512, 512, 512), 32, "naive"),
     ("25c", "f64", (512, 512, 512), 32, "mwd"),
+    ("27b", "f64", (512, 512, 512), 32, "naive"),
+    ("27b", "f64", (512, 512, 512), 32, "mwd"),
+    ("27b", "f32", (512, 512, 512), 32, "naive"),
+    ("27b", "f32", (512, 512, 512), 32, "mwd"),
 ]
-CONSTS = {"7c": [0.4, 0.1], "25c": [0.2, 0.05, 0.04, 0.03, 0.0133]}
+# the box stencil's weights are the workload recipe's (drawn and normalised)
+CONSTS = {"7c": [0.4, 0.1], "25c": [0.2, 0.05, 0.04, 0.03, 0.0133], "27b": None}
 
 
 def socket_power_w():
@@ -75,11 +80,11 @@ def run(seconds):
     print(json.dumps({"case": "idle", "power_w": sum(idle) / len(idle) if idle else None,
                       "samples": len(idle)}), flush=True)
     for st, dt, (nx, ny, nz), T, algo in CASES:
-        u0, _, _ = field_and_coefs(st, nx, ny, nz, seed=0, const_coefs=CONSTS[st])
+        u0, c, _ = field_and_coefs(st, nx, ny, nz, seed=0, const_coefs=CONSTS[st])
         g = torch.from_numpy(u0).to(dev)
         if dt == "f32":
             g = g.to(torch.float32)
-        sw = Sweep(st, dt, nx, ny, nz, CONSTS[st], algo)
+        sw = Sweep(st, dt, nx, ny, nz, [float(x) for x in c], algo)
         b0, b1 = g.clone(), g.clone()
         sw.run(b0, b1, T)
         torch.cuda.synchronize()

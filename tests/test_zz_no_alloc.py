@@ -2,8 +2,9 @@
 through the C ABI: two calls in a row on one device, the second on a smaller
 grid, bit for bit; the blocked sweep of a constant- and a variable-coefficient
 stencil, with relaxed synchronisation (whose error word sits in the fixed
-array too), and the second-order stencil (whose u^{-1} a run may copy into
-the fixed pair); a grid over the fixed limit is refused before any launch."""
+array too), the second-order stencil (whose u^{-1} a run may copy into
+the fixed pair) and the box stencil (three-plane stage rows); a grid over
+the fixed limit is refused before any launch."""
 import numpy as np
 import pytest
 
@@ -46,7 +47,8 @@ def run_both(stencil, dtype, n, T, params):
 @pytest.mark.parametrize("stencil,dtype,params", [("7c", "f64", {"diamond_width": 8}),
                                                   ("7v", "f32", {"diamond_width": 12}),
                                                   ("7c", "f64", {"variant": 2}),
-                                                  ("25l", "f64", {})])
+                                                  ("25l", "f64", {}),
+                                                  ("27b", "f32", {})])
 def test_noalloc_equals_run_twice_second_smaller(stencil, dtype, params):
     for n, T in (((150, 61, 23), 11), ((70, 29, 9), 6)):
         ref, got = run_both(stencil, dtype, n, T, params)
