@@ -410,11 +410,18 @@ def test_dpp_edge_masks_give_the_stage_values(nx):
     """For every block of every x chunk (zero and nonzero halo), lanes whose
     cell is inside the grid get exactly the x neighbours the stage holds:
     the DPP value where the neighbour lane staged its own register value,
-    the stage otherwise (block ends, halo lanes' columns)."""
+    the stage otherwise (block ends, halo lanes' columns).  Only the
+    columns 1 .. XL - 2 need them: from level 1 on the row's outermost
+    columns lie outside the valid span [kR, XL - kR) of level k, and the
+    stored columns [HX, XL - HX) lie inside it at every level up to L - 1.
+    (The kernel masks the outermost lanes too; leaving them unmasked
+    measured no faster.)"""
     import random
-    R, XL = 1, 128
-    HX = R * (12 - 1)
+    R, XL, L = 1, 128, 12
+    HX = R * (L - 1)
     x_own = XL - 2 * HX
+    for k in range(1, L):
+        assert k * R <= HX and XL - HX <= XL - k * R
     rnd = random.Random(nx)
     for zero_halo in (True, False):
         n_chunks = (nx + x_own - 1) // x_own
@@ -438,7 +445,7 @@ def test_dpp_edge_masks_give_the_stage_values(nx):
                 xm, xp = dpp_neighbours(vals, stage, R + cb, rule)
                 for i in range(64):
                     x = x0 + cb + i
-                    if 0 <= x < nx:
+                    if 0 <= x < nx and 0 < cb + i < XL - 1:
                         assert xm[i] == stage[R + cb + i - 1], (nx, chunk, blk, i)
                         assert xp[i] == stage[R + cb + i + 1], (nx, chunk, blk, i)
 
@@ -453,3 +460,14 @@ def test_dpp_edge_masks_without_halo_lanes_fail():
     xm, _ = dpp_neighbours(regs[:64], stage, R, lambda i, side: i == 0 if side == "m" else i == 63)
     i = -x0          # lane of x = 0
     assert xm[i] != stage[R + i - 1]
+
+
+def test_dpp_edge_masks_without_inner_block_ends_fail():
+    # dropping the mask at the end of a 64-lane block inside the row (lane 63
+    # of the first block, whose x + 1 neighbour sits in the next block's lane
+    # 0) hands that lane the DPP fill value instead of the stage value
+    R, XL = 1, 128
+    regs = [float(c + 1) for c in range(XL)]
+    stage = [9.0] + regs + [9.0]
+    _, xp = dpp_neighbours(regs[:64], stage, R, lambda i, side: False)
+    assert xp[63] != stage[R + 64]
