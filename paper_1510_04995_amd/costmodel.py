@@ -14,7 +14,7 @@ All arithmetic of the network (forward, back-propagation, Adam) runs in the
 features, the parameter initialisation and the training loop, with PyTorch
 providing device memory and the stream.
 
-Features of a candidate (20, in this order):
+Features of a candidate (22, in this order):
   0 stencil radius R          1 number of coefficient arrays
   2-4 log2 nx, ny, nz          5 dtype (0 = FP64, 1 = FP32)
   6 diamond width Dw           7 wavefront depth N_F
@@ -27,10 +27,16 @@ Features of a candidate (20, in this order):
   18 log2 of the paper's blocked code balance B_C (bytes per update,
      Section "Memory traffic model"; N_D = 2 + coefficient arrays)
   19 log2 of the redundant x-halo read factor (x tile + 2R(L-1)) / x tile
-They are standardised with the mean and spread of the training set.  The
-last two carry the traffic model across stencils: a problem whose
+  20 log2 of the rounds a diamond row's workgroups take on the 256 CUs
+     (x chunks x diamonds of the row, over the CUs times the workgroups one
+     CU holds by its LDS)
+  21 fill of those rounds (workgroups / (rounds x slots))
+They are standardised with the mean and spread of the training set.
+Features 18 and 19 carry the traffic model across stencils: a problem whose
 coefficient arrays the training set never saw still differs from the
 training problems in B_C, which the training set relates to throughput.
+The last two carry launch quantisation across grids: a tile that fits a
+row's workgroups in one round on one grid can need two on another.
 """
 import math
 
@@ -38,13 +44,15 @@ import numpy as np
 
 from . import girih as G
 
-N_FEATURES = 20
+N_FEATURES = 22
+N_CU = 256
+LDS_PER_CU = 163840
 STENCIL_NCOEF = G.N_COEF
 RADIUS = G.RADIUS
 
 
 def features(stencil, dtype, nx, ny, nz, T, params, lds_bytes):
-    """The 20 raw features of one candidate (see the module docstring)."""
+    """The 22 raw features of one candidate (see the module docstring)."""
     q = params
     v = int(q.get("variant") or 0)
     R, dw, tx = RADIUS[stencil], float(q["diamond_width"]), float(max(1, q["tile_x"]))
@@ -52,12 +60,16 @@ def features(stencil, dtype, nx, ny, nz, T, params, lds_bytes):
     nd = 2 + STENCIL_NCOEF[stencil]
     b_c = 2 * s * R * ((2 * dw - 2 * R) + (nd * dw + 2 * R)) / (dw * dw)
     rho = (tx + 2 * R * (dw / R - 1)) / tx
+    idw = int(q["diamond_width"])
+    tiles = -(-nx // max(1, int(q["tile_x"]))) * ((ny + idw // 2 + idw - 1) // idw)
+    slots = N_CU * max(1, LDS_PER_CU // max(1, int(lds_bytes)))
+    rounds = -(-tiles // slots)
     return [float(RADIUS[stencil]), float(STENCIL_NCOEF[stencil]), math.log2(nx), math.log2(ny), math.log2(nz),
             0.0 if dtype == "f64" else 1.0, float(q["diamond_width"]), float(q["wavefront_depth"] or 1),
             math.log2(max(1, q["tile_x"])), float(q["tile_y"]), math.log2(max(1, q["tile_z"])),
             q["threads_x"] / 64.0, float(q["threads_y"]), float(q.get("cells_per_lane") or 1),
             lds_bytes / 65536.0, math.log2(max(1, T)), float(v & 1), float((v >> 1) & 1), math.log2(b_c),
-            math.log2(rho)]
+            math.log2(rho), math.log2(rounds), tiles / (rounds * slots)]
 
 
 def candidate_table(sweep, T):

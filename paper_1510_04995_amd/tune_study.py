@@ -6,13 +6,15 @@
 
 1. The tuner measures every feasible blocked candidate (exhaustive search) of
    the training problems: 7-point constant 64^3 (T = 16) and 512^3 (T = 64),
-   25-point constant 512^3 (T = 32), each in FP64 and FP32.  Every measured
-   candidate is one training record (features, GLUP/s).
+   25-point constant 512^3 (T = 32) and 7-point variable 256^3 (T = 32),
+   each in FP64 and FP32.  Every measured candidate is one training record
+   (features, GLUP/s).
 2. The cost model is trained on those records (HIP kernels, Adam).
 3. On the problem the model has not seen -- the 7-point variable-coefficient
    stencil (seven coefficient arrays) on 256 x 512 x 1024, T = 64, in FP64
-   and FP32 -- and, as further unseen problems, the constant-coefficient
-   stencils on the same grid, the study compares exhaustive search, the
+   and FP32, a grid and a step count none of the training problems has --
+   and, as further unseen problems, the constant-coefficient stencils on
+   the same grid, the study compares exhaustive search, the
    paper's hill-climbing tuner, the model's top-5 and the paper's "largest
    tile that fits" pick: best measured GLUP/s, number of candidates measured
    and tuning time.
@@ -34,7 +36,8 @@ import numpy as np
 from . import Sweep
 from . import costmodel as C
 
-TRAIN = [("7c", (64, 64, 64), 16), ("7c", (512, 512, 512), 64), ("25c", (512, 512, 512), 32)]
+TRAIN = [("7c", (64, 64, 64), 16), ("7c", (512, 512, 512), 64), ("25c", (512, 512, 512), 32),
+         ("7v", (256, 256, 256), 32)]
 EVAL = [("7v", "f64"), ("7v", "f32"), ("7c", "f64"), ("7c", "f32"), ("25c", "f64")]
 EVAL_GRID = (256, 512, 1024)
 EVAL_T = 64
@@ -69,10 +72,13 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--log", default=None, help="write the training records as JSON lines")
     ap.add_argument("--budget", type=float, default=60.0, help="seconds per exhaustive search")
+    ap.add_argument("--constant-only", action="store_true",
+                    help="train on the constant-coefficient problems only")
     args = ap.parse_args()
 
+    train = [t for t in TRAIN if not (args.constant_only and t[0] == "7v")]
     X, y, rows = [], [], []
-    for st, n, T in TRAIN:
+    for st, n, T in train:
         for dt in ("f64", "f32"):
             sw = Sweep(st, dt, *n, CONSTS[st], "mwd")
             r = timed_tune(sw, "exhaustive", T, args.budget)
@@ -97,7 +103,8 @@ def main():
     say("model: %d records, loss %.4f -> %.4f, median |log error| %.3f, %.1f s" % (len(X), losses[0], losses[-1],
                                                                                   fit_err, t_fit))
     report = {"train_records": len(X), "train_loss_first": float(losses[0]), "train_loss_last": float(losses[-1]),
-              "train_median_abs_log_error": fit_err, "train_seconds": t_fit, "eval": []}
+              "train_median_abs_log_error": fit_err, "train_seconds": t_fit,
+              "train_problems": [[st, list(n), T] for st, n, T in train], "eval": []}
     for st, dt in EVAL:
         res = {"stencil": st, "dtype": dt, "grid": EVAL_GRID, "T": EVAL_T}
         sw = Sweep(st, dt, *EVAL_GRID, CONSTS[st], "mwd")
@@ -135,7 +142,8 @@ def summary(report_path, out_path, command):
              "Command: `%s`" % command, "",
              "Training: every feasible blocked candidate of %s, FP64 and FP32, measured by exhaustive search: "
              "%d records; loss %.4g -> %.4g (log GLUP/s squared), median absolute log error %.3f, %.1f s on the GPU."
-             % (", ".join("%s %s T = %d" % (st, "x".join(str(v) for v in n), T) for st, n, T in TRAIN),
+             % (", ".join("%s %s T = %d" % (st, "x".join(str(v) for v in n), T)
+                          for st, n, T in rep.get("train_problems", TRAIN)),
                 rep["train_records"], rep["train_loss_first"], rep["train_loss_last"],
                 rep["train_median_abs_log_error"], rep["train_seconds"]), "",
              "Evaluation on unseen problems: the GLUP/s of each search's pick, timed again after the "

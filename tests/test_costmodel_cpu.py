@@ -20,12 +20,26 @@ def params(dw, tile_x, variant=0, nf=1, tx=128, vx=1):
 def test_traffic_features_follow_the_papers_model(stencil, dtype, dw, tile_x):
     R = C.RADIUS[stencil]
     f = C.features(stencil, dtype, 512, 512, 512, 64, params(dw, tile_x), 100000)
-    assert len(f) == C.N_FEATURES == 20
+    assert len(f) == C.N_FEATURES == 22
     nd = 2 + C.STENCIL_NCOEF[stencil]
     word = 8 if dtype == "f64" else 4
     assert 2 ** f[18] == pytest.approx(models.code_balance(dw, R, nd, word_bytes=word), rel=1e-12)
     L = dw // R
     assert 2 ** f[19] == pytest.approx((tile_x + 2 * R * (L - 1)) / tile_x, rel=1e-12)
+
+
+def test_launch_round_features():
+    """7c FP64 on 512^3, Dw = 12 (44 diamonds in the larger row offset):
+    x tile 103 gives 5 chunks, 220 workgroups, one round of the 256 CUs at
+    one workgroup per CU (102960 B of LDS), filled 220/256; x tile 86 gives
+    6 chunks, 264 workgroups, two rounds; a 50 KB workgroup (three per CU)
+    takes 768 slots."""
+    f = C.features("7c", "f64", 512, 512, 512, 64, params(12, 103), 102960)
+    assert (2 ** f[20], f[21]) == (1, pytest.approx(220 / 256))
+    f = C.features("7c", "f64", 512, 512, 512, 64, params(12, 86), 102960)
+    assert (2 ** f[20], f[21]) == (2, pytest.approx(264 / 512))
+    f = C.features("7c", "f64", 512, 512, 512, 64, params(12, 86), 50000)
+    assert (2 ** f[20], f[21]) == (1, pytest.approx(264 / 768))
 
 
 def test_variant_bits():
