@@ -272,7 +272,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     w = WORKLOADS[args.workload]
-    if w.stencil not in ("7c", "25c", "7v", "25v", "25l"):
+    if w.stencil not in ("7c", "25c", "7v", "25v", "25l", "27b"):
         print("unknown stencil of workload %s" % w.name, file=sys.stderr)
         sys.exit(2)
     if args.dtype != "f64" and (not args.no_compare or not args.no_cpu):
