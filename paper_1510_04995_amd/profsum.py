@@ -36,7 +36,8 @@ FP64_PEAK_TFLOPS = 78.6
 LDS_BYTES_PER_CLK = 128
 
 
-STENCIL_CLASS = {"7c": "Stencil7C", "7v": "Stencil7V", "25c": "Stencil25C", "25v": "Stencil25V"}
+STENCIL_CLASS = {"7c": "Stencil7C", "7v": "Stencil7V", "25c": "Stencil25C", "25v": "Stencil25V", "25l": "Stencil25L",
+                 "27b": "Stencil27B"}
 
 
 def _plan_key(b):
