@@ -250,8 +250,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-suite", action="store_true", help="skip the other workloads (per_stencil)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    help="workload of the timed runs (default: the headline 7-point constant 512^3; another "
-                         "first-order workload serves profiling runs of its blocked kernel)")
+                    help="workload of the timed runs (default: the headline 7-point constant 512^3; any other "
+                         "workload serves profiling runs of its blocked kernel)")
     ap.add_argument("--dtype", default="f64", choices=("f64", "f32"),
                     help="element type of the timed runs (FP64 unless profiling the FP32 kernels)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
