@@ -1,5 +1,5 @@
 """Measured HBM bytes per lattice update against the traffic model, over
-diamond widths: the GPU counterpart of the paper's study of code balance
+diamond widths and sweep kernels: the GPU counterpart of the paper's study of code balance
 versus diamond width (Section "Memory traffic model" and the results that
 compare measured and modelled bytes per update).
 
@@ -35,9 +35,16 @@ CASES = [
     ("25c", "f64", (512, 512, 512), 32, "naive", None),
     ("25c", "f64", (512, 512, 512), 32, "mwd", {"diamond_width": 8, "cells_per_lane": 1, "threads_x": 128}),
     ("25c", "f64", (512, 512, 512), 32, "mwd", {"diamond_width": 16, "cells_per_lane": 1, "threads_x": 64}),
+    # the naive register columns (FP32 defaults of the star stencils) and the box stencil
+    ("25c", "f32", (512, 512, 512), 32, "naive", None),
+    ("27b", "f64", (512, 512, 512), 32, "naive", None),
+    ("27b", "f32", (512, 512, 512), 32, "naive", None),
+    ("27b", "f64", (512, 512, 512), 32, "mwd", None),
 ]
-CONSTS = {"7c": [0.4, 0.1], "25c": [0.2, 0.05, 0.04, 0.03, 0.0133]}
-SWEEP_KERNELS = ("mwd_row_kernel", "naive_step_kernel", "naive_tile_kernel")
+# the box stencil's weights are the workload recipe's (drawn and normalised)
+CONSTS = {"7c": [0.4, 0.1], "25c": [0.2, 0.05, 0.04, 0.03, 0.0133], "27b": None}
+SWEEP_KERNELS = ("mwd_row_kernel", "naive_step_kernel", "naive_tile_kernel", "naive_box_cols_kernel",
+                 "naive_star_cols_kernel")
 COPY_KERNEL = "copyBuffer"
 
 
@@ -47,17 +54,17 @@ def run(copy_mib):
     from workloads import field_and_coefs
     dev = torch.device("cuda:0")
     for st, dt, (nx, ny, nz), T, algo, prm in CASES:
-        u0, _, _ = field_and_coefs(st, nx, ny, nz, seed=0, const_coefs=CONSTS[st])
+        u0, c, _ = field_and_coefs(st, nx, ny, nz, seed=0, const_coefs=CONSTS[st])
         g = torch.from_numpy(u0).to(dev)
         if dt == "f32":
             g = g.to(torch.float32)
-        sw = Sweep(st, dt, nx, ny, nz, CONSTS[st], algo, prm)
+        sw = Sweep(st, dt, nx, ny, nz, [float(x) for x in c], algo, prm)
         info = sw.info()
         b0, b1 = g.clone(), g.clone()
         sw.run(b0, b1, T)
         torch.cuda.synchronize()
         q = info["params"]
-        R = 1 if st.startswith("7") else 4
+        R = 4 if st.startswith("25") else 1
         launches = T if algo == "naive" else (T - 1) // (q["diamond_width"] // (2 * R)) + 2
         print(json.dumps({"stencil": st, "dtype": dt, "grid": [nx, ny, nz], "T": T, "algo": algo,
                           "params": {k: q[k] for k in ("diamond_width", "tile_x", "threads_x", "cells_per_lane")},
@@ -101,7 +108,7 @@ def summary(fetch_csv, write_csv, run_log, copy_mib, out_path, command):
             i += c["launches"]
             per.setdefault(j, {})[counter] = kib * 1024.0 * scale
         per["scale_" + counter] = scale
-    lines = ["# Measured HBM bytes per update against the model, over diamond widths", "",
+    lines = ["# Measured HBM bytes per update against the model, over diamond widths and sweep kernels", "",
              "Command: `%s`" % command, "",
              "Counters `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch) summed over every sweep launch of a case, "
              "each scaled by what it reads for a %s MiB device copy in the same run (factors %.3f and %.3f); "
