@@ -635,11 +635,13 @@ def test_mwd_odd_size_twin(stencil, dtype, n, T):
 @pytest.mark.parametrize("name,dtype", [("25pt-const-512", "f64"), ("25pt-var-384", "f64"), ("25pt-var-384", "f32"),
                                         ("7pt-var-256x512x1024", "f64"), ("7pt-var-256x512x1024", "f32"),
                                         ("25pt-leapfrog-512", "f64"), ("25pt-leapfrog-512", "f32"),
-                                        ("27pt-box-512", "f64")])
+                                        ("27pt-box-512", "f64"), ("27pt-box-512", "f32"),
+                                        ("25pt-const-512", "f32"), ("7pt-const-512", "f32")])
 def test_full_size_workloads(name, dtype):
-    """The other workloads at their full sizes in their default launch
-    configurations: the blocked sweep (where one exists) and the naive sweep
-    equal the oracle (same precision) in every element."""
+    """The workloads at their full sizes in their default launch
+    configurations (in FP32 the naive sweeps of the 7-point, 25-point and box
+    stencils are register columns): the blocked and the naive sweep equal
+    the oracle (same precision) in every element."""
     import paper_1510_04995_amd as P
     from tests.gpu_util import torch_dev
     from workloads import WORKLOADS
